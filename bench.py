@@ -1,0 +1,182 @@
+"""Benchmark: K elements/s of the MASTER coupling matrices K^TT, K^TE, K^EE,
+K^BB at lmax = 6000 on one MI355X, with the roofline of the l3-reduction
+kernel and the CPU oracle timed on a bounded sample beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32c|both]
+
+A step is one couple_matrix call (window scaling -> l3 reduction -> fill) for
+all four spectra of the synthetic lmax = 6000 window (inputs resident in HBM,
+output 4 x 6001^2 float64 written to HBM).  The timed region is bracketed by
+torch.cuda.synchronize() on both sides; per-kernel durations come from HIP
+events the library records on the call's stream.  One JSON line is printed.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz, fp64 and non-packed fp32
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_TRIPLE_POL = 16  # TT 5 + TE/EE 11
+FLOP_PER_TRIPLE_TT = 5
+
+
+def triples(lmax: int) -> int:
+    """Even-L triples with l1 <= l2: C(lmax + 3, 3)."""
+    return math.comb(lmax + 3, 3)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="both", choices=("fp64", "fp32c", "both"))
+    ap.add_argument("--lmax", type=int, default=6000)
+    ap.add_argument("--cpu-rows", type=int, default=60, help="oracle rows timed for cpu_baseline (0: skip)")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How it would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_15605_amd import couple, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    lmax = args.lmax
+    spectra = ("TT", "TE", "EE", "BB")
+    W = synth.workload_windows(2, lmax=lmax)
+    dW = [torch.as_tensor(w).cuda() for w in W]
+    ctx = couple.couple_init(lmax)
+    out = torch.empty((4, lmax + 1, lmax + 1), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    precisions = ["fp32c", "fp64"] if args.precision == "both" else [args.precision]
+    n_el = 4 * (lmax + 1) ** 2
+    T = triples(lmax)
+    results = {}
+    for prec in precisions:
+        try:
+            couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=prec, out=out, stream=stream)
+        except couple.CoupleError as e:
+            if e.code == couple.COUPLE_ENOTSUP:
+                results[prec] = {"status": "not available: %s" % e}
+                continue
+            raise
+        for _ in range(max(0, args.warmup - 1)):
+            couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=prec, out=out, stream=stream)
+        torch.cuda.synchronize()
+        couple.couple_profile(ctx, True)
+        t0 = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=prec, out=out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = couple.couple_profile_read(ctx)
+        couple.couple_profile(ctx, False)
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        strip_ms, strip_n = prof["strip"]
+        strip_avg = strip_ms / max(1, strip_n)
+        flops = FLOP_PER_TRIPLE_POL * T
+        r = {
+            "ms_per_step": ms_step,
+            "wall_ms_per_step": 1e3 * wall / args.steps,
+            "k_elements_per_s": n_el / (ms_step * 1e-3),
+            "kernel_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+            "strip_tflops": flops / (strip_avg * 1e-3) / 1e12,
+        }
+        results[prec] = r
+        print("[bench] %s: %.3f ms/step, strip %.3f ms, %.2f TFLOP/s alg" %
+              (prec, ms_step, strip_avg, r["strip_tflops"]), file=sys.stderr, flush=True)
+
+    # oracle: CPU baseline on a bounded sample of rows, and the error of each path on it
+    cpu = None
+    if args.cpu_rows > 0:
+        from oracle import bulk
+        rows = synth.sample_rows(lmax, fraction=args.cpu_rows / (lmax + 1), seed=6000, minimum=args.cpu_rows)
+        rows = rows[:args.cpu_rows]
+        n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        Kr, Ar = bulk.coupling_rows(lmax, *W, rows=rows, spectra=spectra, n_threads=n_threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(rows) * (lmax + 1) * 4 / dt, "unit": "K elements/s", "cores": n_threads,
+               "kind": "oracle",
+               "sample": "%d seeded rows of %d (all 4 spectra, all l2) at lmax=%d: %.1f s on %d threads of %s"
+                         % (len(rows), lmax + 1, lmax, dt, n_threads, cpu_model())}
+        if not args.no_check:
+            rows_t = torch.as_tensor(rows.astype(np.int64)).cuda()
+            for prec in precisions:
+                if "ms_per_step" not in results[prec]:
+                    continue
+                couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=prec, out=out, stream=stream)
+                torch.cuda.synchronize()
+                K = out[:, rows_t, :].cpu().numpy()
+                errs = {}
+                for i, s in enumerate(spectra):
+                    nz = Ar[i] > 0
+                    errs[s] = float(np.max(np.abs(K[i][nz] - Kr[i][nz]) / Ar[i][nz]))
+                    assert np.all(K[i][~nz] == 0.0)
+                results[prec]["max_rel_err"] = errs
+
+    head = "fp32c" if "ms_per_step" in results.get("fp32c", {}) else "fp64"
+    h = results[head]
+    strip_avg = h["kernel_ms"]["strip"]
+    achieved = FLOP_PER_TRIPLE_POL * T / (strip_avg * 1e-3) / 1e12
+    line = {
+        "metric": "K elements/s at lmax=6000 TT+pol, FP32-comp/MFMA vs FP64 plain, max rel err",
+        "value": h["k_elements_per_s"],
+        "unit": "K elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "pol4_lmax6000: TT,TE,EE,BB at lmax=6000, one synthetic window "
+                               "(W_0=4pi*0.4, (l+1)^-2 exp(-(l/1500)^2) lognormal 0.1, seeds 2000/2001/2002)",
+                   "lmax": lmax, "spectra": list(spectra), "precision": head,
+                   "triples": T, "elements_per_step": n_el},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "strip (l3 reduction)", "flop_per_triple": FLOP_PER_TRIPLE_POL},
+        "cpu_baseline": cpu,
+        "precisions": results,
+    }
+    print(json.dumps(line), flush=True)
+    couple.couple_free(ctx)
+
+
+if __name__ == "__main__":
+    main()

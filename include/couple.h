@@ -1,0 +1,160 @@
+/*
+ * couple.h -- C ABI of libcouple: MASTER mode-coupling matrices on MI355X.
+ *
+ * Computes, for a survey window with power spectra W_TT, W_TP, W_PP,
+ *
+ *   K^X_{l1 l2} = (2 l2 + 1) Xi_X(l1, l2),
+ *   Xi_X(l1, l2) = 1/(4 pi) sum_{l3} (2 l3 + 1) W^X_{l3} S^X(l1, l2, l3),
+ *
+ *   S^TT = (l1 l2 l3; 0 0 0)^2                              Sec. 2, eq. K_TT
+ *   S^TE = [(1+(-1)^L)/2] (l1 l2 l3; 0 0 0)(l1 l2 l3; -2 2 0)   App. A, eq. Sig_TE
+ *   S^EE = S^BB = [(1+(-1)^L)/2]^2 (l1 l2 l3; -2 2 0)^2      Sec. 2, eq. K_EE; App. A
+ *
+ * (L = l1 + l2 + l3; W^TT = W_TT, W^TE = W_TP, W^EE = W^BB = W_PP), with every
+ * 3j value taken from look-up tables of g(p) = (2p)!/(2^{2p} (p!)^2) built by
+ * the recurrence of Sec. 3.1 (eqs. 000_sq_main, gdef, g_rec), and the
+ * (-2 2 0) symbol reduced to the (0 0 0) one in closed form (Sec. 3.2,
+ * App. B.3, eq. 022_linear_closedform).
+ *
+ * Conventions for every entry point
+ *   - Return value: COUPLE_OK (0) on success, a negative COUPLE_E* code on
+ *     failure.  Nothing throws or aborts.  couple_last_error() gives the text
+ *     of the last failure on that context.
+ *   - Pointers to window spectra and outputs are DEVICE pointers (e.g. the
+ *     data_ptr() of a torch-ROCm tensor on the context's device), owned by the
+ *     caller, float64, contiguous.  The library never frees them.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL means
+ *     the legacy default stream); results are ready when the stream is.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *   - Calls on one context must not overlap in time on different streams:
+ *     they share the context's workspace.
+ *   - Output layout: out[n_spec][lmax+1][lmax+1], row-major (row l1, column
+ *     l2), spectra in the order TT, TE, EE, BB restricted to those requested.
+ *     Polarization rows and columns 0 and 1 are exactly 0 (the (-2 2 0)
+ *     symbol vanishes for l < 2).  K^BB is bitwise equal to K^EE.
+ */
+#ifndef COUPLE_H
+#define COUPLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct couple_ctx couple_ctx;
+
+enum couple_status {
+    COUPLE_OK = 0,
+    COUPLE_EINVAL = -1,   /* bad argument (detected on the host, nothing enqueued) */
+    COUPLE_ENOMEM = -2,   /* device or host allocation failed (couple_init only)   */
+    COUPLE_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed            */
+    COUPLE_ENOTSUP = -4   /* valid request this build does not implement           */
+};
+
+/* spectra bit mask */
+enum couple_spectrum { COUPLE_TT = 1, COUPLE_TE = 2, COUPLE_EE = 4, COUPLE_BB = 8 };
+
+/* arithmetic of the l3 reduction */
+enum couple_precision {
+    COUPLE_FP64 = 0,   /* float64 throughout                                          */
+    COUPLE_FP32C = 1   /* float32 terms with compensated accumulation; float64 tables,
+                          window scaling and final rescale                             */
+};
+
+/*
+ * couple_init -- build the look-up tables on the current HIP device and size
+ * the workspace for every later call with lmax <= lmax_max.
+ *   lmax_max : 0 <= lmax_max <= COUPLE_LMAX_LIMIT.
+ *   ctx      : receives the new context (owned by the caller; release with
+ *              couple_free).
+ * Tables (Sec. 3.1): g(p) for p <= lmax_max and 1/((2p+1) g(p)) for
+ * p <= 2 lmax_max (the paper's 1/(J+1) factor folded in, J + 1 = 2p + 1),
+ * plus c_l = [(l-1) l (l+1) (l+2)]^{-1/2} (the 1/(lambda eta) factor of
+ * App. B.3).  They are generated on the device by the g recurrence in
+ * double-double arithmetic and rounded once to float64 and float32.
+ * Workspace: 3 (lmax_max+1)(lmax_max+2)/2 float64 for the symmetric kernels
+ * Xi plus 6 (2 lmax_max + 1) words for the scaled windows.
+ * Errors: EINVAL (bad lmax_max, NULL ctx), ENOMEM, EDEVICE.
+ */
+#define COUPLE_LMAX_LIMIT 16384
+int couple_init(int lmax_max, couple_ctx **ctx);
+
+/* couple_free -- release a context (NULL is a no-op).  Synchronises the device. */
+void couple_free(couple_ctx *ctx);
+
+/* couple_last_error -- NUL-terminated text of the last failure on ctx (owned
+ * by ctx, valid until the next call on it); "" if none.  ctx may be NULL, in
+ * which case the text of the last failed couple_init is returned. */
+const char *couple_last_error(const couple_ctx *ctx);
+
+/*
+ * couple_matrix -- full coupling matrices (Sec. 2 eqs. K_TT, K_EE; App. A).
+ *   W_TT, W_TP, W_PP : device float64 window spectra W_l, l = 0 .. w_len-1.
+ *                      Only those the requested spectra use must be non-NULL
+ *                      (TT -> W_TT, TE -> W_TP, EE/BB -> W_PP).
+ *   w_len            : >= 2*lmax + 1 (W_L is needed for L <= 2 lmax, Sec. 4).
+ *   lmax             : 0 <= lmax <= lmax_max of ctx.
+ *   spectra          : non-empty OR of COUPLE_TT/TE/EE/BB.
+ *   precision        : COUPLE_FP64 or COUPLE_FP32C.
+ *   out              : device float64, popcount(spectra) * (lmax+1)^2 entries,
+ *                      8-byte aligned; fully overwritten.
+ *   stream           : hipStream_t to enqueue on.
+ * Errors: EINVAL (NULL ctx/out/needed window, lmax or w_len out of range,
+ * empty or unknown spectra bits, unknown precision, misaligned out), EDEVICE.
+ */
+int couple_matrix(couple_ctx *ctx, const double *W_TT, const double *W_TP, const double *W_PP,
+                  int w_len, int lmax, unsigned spectra, int precision, double *out, void *stream);
+
+/*
+ * couple_band -- band-limited coupling matrices (Sec. 4.3): only
+ * l3_lo <= l3 <= l3_hi enters the l3 sum, which is exact when W vanishes
+ * outside that band.  Elements with |l1 - l2| > l3_hi are exactly 0 and
+ * cost nothing.
+ *   l3_lo, l3_hi : 0 <= l3_lo <= l3_hi.
+ *   bin_edges    : NULL for the unbinned [n_spec][lmax+1][lmax+1] output, or a
+ *                  HOST array of n_bins+1 strictly increasing multipoles with
+ *                  0 <= bin_edges[0] and bin_edges[n_bins] <= lmax+1; bin b is
+ *                  [bin_edges[b], bin_edges[b+1]).  Binned output is
+ *                  out[n_spec][n_bins][n_bins] with
+ *                  K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2}
+ *                  (uniform average over the row bin, sum over the column bin).
+ *   other arguments as couple_matrix (w_len >= min(l3_hi, 2 lmax) + 1).
+ * Errors: as couple_matrix, plus EINVAL for a bad band or bin list.
+ */
+int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const double *W_TP,
+                const double *W_PP, int w_len, int lmax, unsigned spectra, int precision,
+                const int *bin_edges, int n_bins, double *out, void *stream);
+
+/*
+ * couple_tables -- copy the context's look-up tables to HOST buffers (for
+ * inspection and tests).  Any pointer may be NULL to skip that table.
+ *   g    : lmax_max + 1 float64,   g[p] = g(p)                  (eq. gdef)
+ *   h    : 2 lmax_max + 1 float64, h[p] = 1/((2p+1) g(p))        (eq. 000_sq_main)
+ *   cl   : lmax_max + 1 float64,   cl[l] = [(l-1) l (l+1)(l+2)]^{-1/2}, 0 for l < 2
+ *   gf, hf : float32 roundings of g and h (lengths as g and h)
+ * Synchronises the device.  Errors: EINVAL (NULL ctx), EDEVICE.
+ */
+int couple_tables(const couple_ctx *ctx, double *g, double *h, double *cl, float *gf, float *hf);
+
+/* couple_lmax_max -- the lmax_max ctx was built for, or -1 for NULL. */
+int couple_lmax_max(const couple_ctx *ctx);
+
+/*
+ * Measurement hooks (not part of the method).  couple_profile(ctx, 1) clears
+ * the counters and makes every later call record a HIP event pair around each
+ * of its kernels on the call's stream; couple_profile(ctx, 0) stops.
+ * couple_profile_read waits for the recorded events and returns, per stage,
+ * the summed kernel milliseconds and the number of launches:
+ *   stage 0 = window scaling, 1 = l3 reduction (strip kernel),
+ *   2 = fill / bin.
+ * ms and counts are HOST arrays of COUPLE_N_STAGES entries (either may be
+ * NULL).  Errors: EINVAL (NULL ctx), EDEVICE.
+ */
+#define COUPLE_N_STAGES 3
+int couple_profile(couple_ctx *ctx, int enable);
+int couple_profile_read(couple_ctx *ctx, double *ms, int *counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COUPLE_H */

@@ -1,0 +1,327 @@
+// Host side of the C ABI declared in include/couple.h: argument checks,
+// context ownership and the launch sequence
+//   scale windows -> strip (l3 reduction on the upper triangle) -> fill or bin.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "couple_internal.hpp"
+
+namespace {
+
+std::string g_init_error;  // text of the last failed couple_init (no context to hold it)
+
+int fail(couple_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+int hip_fail(couple_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, COUPLE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// Fold recorded event pairs into the per-stage totals.
+hipError_t drain_marks(couple_ctx* c) {
+    hipError_t first = hipSuccess;
+    for (auto& m : c->marks) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(m.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.start, m.stop);
+        if (e == hipSuccess) {
+            c->prof_ms[m.stage] += ms;
+            c->prof_count[m.stage] += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    c->marks.clear();
+    return first;
+}
+
+// Event pair around one launch when the measurement hook is on.
+struct Timed {
+    couple_ctx* c;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(couple_ctx* c_, hipStream_t s_, int stage_) : c(c_), s(s_), stage(stage_) {
+        if (!c->profiling) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+            hipEventRecord(a, s) != hipSuccess) {
+            a = b = nullptr;
+        }
+    }
+    ~Timed() {
+        if (!a) return;
+        if (hipEventRecord(b, s) == hipSuccess) {
+            c->marks.push_back({a, b, stage});
+        } else {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    }
+};
+
+void release(couple_ctx* c) {
+    if (!c) return;
+    (void)drain_marks(c);
+    (void)hipFree(c->g_pad);
+    (void)hipFree(c->h_pad);
+    (void)hipFree(c->gf_pad);
+    (void)hipFree(c->hf_pad);
+    (void)hipFree(c->cl);
+    (void)hipFree(c->xi);
+    (void)hipFree(c->wp);
+    (void)hipFree(c->wpf);
+    (void)hipFree(c->edges_dev);
+    if (c->edges_host) (void)hipHostFree(c->edges_host);
+    delete c;
+}
+
+// Order of outputs (TT, TE, EE, BB) -> Xi source (TT 0, TE 1, EE/BB 2).
+int output_sources(unsigned spectra, int* src) {
+    int n = 0;
+    if (spectra & COUPLE_TT) src[n++] = 0;
+    if (spectra & COUPLE_TE) src[n++] = 1;
+    if (spectra & COUPLE_EE) src[n++] = 2;
+    if (spectra & COUPLE_BB) src[n++] = 2;
+    return n;
+}
+
+// Checks shared by couple_matrix and couple_band.
+int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const double* W_PP, int lmax,
+                 unsigned spectra, int precision, const double* out) {
+    if (lmax < 0 || lmax > ctx->lmax_max)
+        return fail(ctx, COUPLE_EINVAL, "lmax=%d outside [0, lmax_max=%d]", lmax, ctx->lmax_max);
+    if (spectra == 0 || (spectra & ~0xFu))
+        return fail(ctx, COUPLE_EINVAL, "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB",
+                    spectra);
+    if (precision != COUPLE_FP64 && precision != COUPLE_FP32C)
+        return fail(ctx, COUPLE_EINVAL, "unknown precision %d", precision);
+    if ((spectra & COUPLE_TT) && !W_TT) return fail(ctx, COUPLE_EINVAL, "TT requested but W_TT is NULL");
+    if ((spectra & COUPLE_TE) && !W_TP) return fail(ctx, COUPLE_EINVAL, "TE requested but W_TP is NULL");
+    if ((spectra & (COUPLE_EE | COUPLE_BB)) && !W_PP)
+        return fail(ctx, COUPLE_EINVAL, "EE/BB requested but W_PP is NULL");
+    if (!out) return fail(ctx, COUPLE_EINVAL, "out is NULL");
+    if (reinterpret_cast<uintptr_t>(out) % alignof(double))
+        return fail(ctx, COUPLE_EINVAL, "out is not 8-byte aligned");
+    return COUPLE_OK;
+}
+
+int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const double* W_PP, int lmax,
+                  unsigned spectra, int precision, int l3_lo, int l3_hi, hipStream_t s) {
+    const bool pol = (spectra & (COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0;
+    // windows are needed for l3 <= min(l3_hi, 2 lmax)
+    const int n = std::min(l3_hi, 2 * lmax) + 1;
+    hipError_t e;
+    {
+        Timed t(ctx, s, 0);
+        e = couple::launch_scale_windows(ctx, (spectra & COUPLE_TT) ? W_TT : nullptr,
+                                         (spectra & COUPLE_TE) ? W_TP : nullptr,
+                                         (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
+    {
+        Timed t(ctx, s, 1);
+        e = couple::launch_strip(ctx, lmax, pol, precision, l3_lo, std::min(l3_hi, 2 * lmax), s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "strip launch");
+    return COUPLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int couple_init(int lmax_max, couple_ctx** out_ctx) {
+    if (!out_ctx) return fail(nullptr, COUPLE_EINVAL, "ctx pointer is NULL");
+    *out_ctx = nullptr;
+    if (lmax_max < 0 || lmax_max > COUPLE_LMAX_LIMIT)
+        return fail(nullptr, COUPLE_EINVAL, "lmax_max=%d outside [0, %d]", lmax_max, COUPLE_LMAX_LIMIT);
+    couple_ctx* c = new (std::nothrow) couple_ctx();
+    if (!c) return fail(nullptr, COUPLE_ENOMEM, "host allocation of the context failed");
+    c->lmax_max = lmax_max;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, COUPLE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    const size_t pad = couple::kTablePad;
+    const size_t ng = lmax_max + 1 + 2 * pad, nh = 2 * (size_t)lmax_max + 1 + 2 * pad;
+    const size_t nw = 3 * (2 * (size_t)lmax_max + 1);
+    struct {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&c->g_pad, ng * sizeof(double)},   {(void**)&c->h_pad, nh * sizeof(double)},
+        {(void**)&c->gf_pad, ng * sizeof(float)},   {(void**)&c->hf_pad, nh * sizeof(float)},
+        {(void**)&c->cl, (lmax_max + 1) * sizeof(double)},
+        {(void**)&c->xi, 3 * (size_t)couple::tri_size(lmax_max) * sizeof(double)},
+        {(void**)&c->wp, nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
+        {(void**)&c->edges_dev, (lmax_max + 2) * sizeof(int)},
+    };
+    for (auto& a : allocs) {
+        e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            release(c);
+            return fail(nullptr, COUPLE_ENOMEM, "hipMalloc of %zu bytes: %s", a.bytes, hipGetErrorString(e));
+        }
+    }
+    e = hipHostMalloc((void**)&c->edges_host, (lmax_max + 2) * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, COUPLE_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    e = couple::launch_build_tables(c, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, COUPLE_EDEVICE, "table build: %s", hipGetErrorString(e));
+    }
+    *out_ctx = c;
+    return COUPLE_OK;
+}
+
+void couple_free(couple_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    release(ctx);
+}
+
+const char* couple_last_error(const couple_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+int couple_lmax_max(const couple_ctx* ctx) { return ctx ? ctx->lmax_max : -1; }
+
+int couple_matrix(couple_ctx* ctx, const double* W_TT, const double* W_TP, const double* W_PP, int w_len,
+                  int lmax, unsigned spectra, int precision, double* out, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    int rc = check_common(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, out);
+    if (rc) return rc;
+    if (w_len < 2 * lmax + 1)
+        return fail(ctx, COUPLE_EINVAL, "w_len=%d < 2*lmax+1=%d (W_L is needed up to L = 2 lmax)", w_len,
+                    2 * lmax + 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = run_reduction(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, 0, 2 * lmax, s);
+    if (rc) return rc;
+    int src[4];
+    const int n_out = output_sources(spectra, src);
+    hipError_t e;
+    {
+        Timed t(ctx, s, 2);
+        e = couple::launch_fill(ctx, lmax, lmax, src, n_out, out, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "fill launch");
+    return COUPLE_OK;
+}
+
+int couple_band(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP,
+                const double* W_PP, int w_len, int lmax, unsigned spectra, int precision, const int* bin_edges,
+                int n_bins, double* out, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    int rc = check_common(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, out);
+    if (rc) return rc;
+    if (l3_lo < 0 || l3_hi < l3_lo)
+        return fail(ctx, COUPLE_EINVAL, "bad l3 band [%d, %d]", l3_lo, l3_hi);
+    const int hi = std::min(l3_hi, 2 * lmax);
+    if (w_len < hi + 1) return fail(ctx, COUPLE_EINVAL, "w_len=%d < %d", w_len, hi + 1);
+    if (bin_edges) {
+        if (n_bins < 1 || n_bins > lmax + 1)
+            return fail(ctx, COUPLE_EINVAL, "n_bins=%d outside [1, lmax+1]", n_bins);
+        if (bin_edges[0] < 0 || bin_edges[n_bins] > lmax + 1)
+            return fail(ctx, COUPLE_EINVAL, "bin edges must lie in [0, lmax+1]");
+        for (int b = 0; b < n_bins; ++b)
+            if (bin_edges[b + 1] <= bin_edges[b])
+                return fail(ctx, COUPLE_EINVAL, "bin edges must be strictly increasing (at %d)", b);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int src[4];
+    const int n_out = output_sources(spectra, src);
+    const int dmax = std::min(lmax, hi);
+    if (l3_lo <= hi) {
+        rc = run_reduction(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, l3_lo, hi, s);
+        if (rc) return rc;
+    }
+    hipError_t e;
+    if (l3_lo > hi) {
+        // empty band: every element is 0
+        const size_t n = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
+        e = couple::launch_zero(out, n, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "zero fill launch");
+        return COUPLE_OK;
+    }
+    if (bin_edges) {
+        // stage the edges through pinned memory; the copy is ordered on s
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "stream sync before edge upload");
+        std::memcpy(ctx->edges_host, bin_edges, (n_bins + 1) * sizeof(int));
+        e = hipMemcpyAsync(ctx->edges_dev, ctx->edges_host, (n_bins + 1) * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "edge upload");
+        {
+            Timed t(ctx, s, 2);
+            e = couple::launch_bin(ctx, lmax, dmax, src, n_out, ctx->edges_dev, n_bins, out, s);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "bin launch");
+    } else {
+        {
+            Timed t(ctx, s, 2);
+            e = couple::launch_fill(ctx, lmax, dmax, src, n_out, out, s);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "fill launch");
+    }
+    return COUPLE_OK;
+}
+
+int couple_tables(const couple_ctx* ctx, double* g, double* h, double* cl, float* gf, float* hf) {
+    if (!ctx) return COUPLE_EINVAL;
+    couple_ctx* c = const_cast<couple_ctx*>(ctx);
+    const size_t pad = couple::kTablePad;
+    const size_t ng = ctx->lmax_max + 1, nh = 2 * (size_t)ctx->lmax_max + 1;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && g) e = hipMemcpy(g, ctx->g_pad + pad, ng * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h) e = hipMemcpy(h, ctx->h_pad + pad, nh * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && cl) e = hipMemcpy(cl, ctx->cl, ng * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && gf) e = hipMemcpy(gf, ctx->gf_pad + pad, ng * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && hf) e = hipMemcpy(hf, ctx->hf_pad + pad, nh * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "table copy");
+    return COUPLE_OK;
+}
+
+int couple_profile(couple_ctx* ctx, int enable) {
+    if (!ctx) return COUPLE_EINVAL;
+    hipError_t e = drain_marks(ctx);
+    for (int i = 0; i < COUPLE_N_STAGES; ++i) {
+        ctx->prof_ms[i] = 0.0;
+        ctx->prof_count[i] = 0;
+    }
+    ctx->profiling = enable != 0;
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile reset");
+    return COUPLE_OK;
+}
+
+int couple_profile_read(couple_ctx* ctx, double* ms, int* counts) {
+    if (!ctx) return COUPLE_EINVAL;
+    hipError_t e = drain_marks(ctx);
+    for (int i = 0; i < COUPLE_N_STAGES; ++i) {
+        if (ms) ms[i] = ctx->prof_ms[i];
+        if (counts) counts[i] = ctx->prof_count[i];
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile read");
+    return COUPLE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the libcouple translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "couple.h"
+
+namespace couple {
+
+// Lanes of a wavefront on CDNA4.
+constexpr int kWave = 64;
+
+// Number of consecutive l1 values a lane of the strip kernel owns.  The
+// G/H windows slide by one per l3 step, so each step loads one new G and
+// one new H value per lane for R terms.
+constexpr int kStripR = 4;
+
+// l3 steps staged in LDS per chunk by the strip kernel.
+constexpr int kStripChunk = 128;
+
+// Zero guard band around the device copies of g(p) and 1/((2p+1)g(p)).
+constexpr int kTablePad = 64;
+
+// Offset of diagonal d of the packed upper-triangle store for lmax:
+// diagonal d holds Xi(l1, l1 + d) for l1 = 0 .. lmax - d.
+__host__ __device__ inline long long diag_offset(int lmax, int d) {
+    return (long long)d * (lmax + 1) - (long long)d * (d - 1) / 2;
+}
+__host__ __device__ inline long long tri_size(int lmax) {
+    return (long long)(lmax + 1) * (lmax + 2) / 2;
+}
+
+}  // namespace couple
+
+struct couple_ctx {
+    int device = 0;
+    int lmax_max = 0;
+    // look-up tables (device); g and h carry kTablePad zeros on both sides
+    double* g_pad = nullptr;     // g(p),            p = -pad .. lmax_max + pad
+    double* h_pad = nullptr;     // 1/((2p+1)g(p)),  p = -pad .. 2 lmax_max + pad
+    float* gf_pad = nullptr;
+    float* hf_pad = nullptr;
+    double* cl = nullptr;        // c_l, l = 0 .. lmax_max
+    // workspace
+    double* xi = nullptr;        // 3 packed upper triangles (TT, TE, EE)
+    double* wp = nullptr;        // scaled windows (2l+1) W_l / (4 pi), 3 x (2 lmax_max + 1)
+    float* wpf = nullptr;        // float32 copies
+    int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
+    int* edges_host = nullptr;   // pinned staging for the bin edges
+    std::string err;
+    // measurement hook: event pairs recorded around each kernel
+    bool profiling = false;
+    struct Mark {
+        hipEvent_t start, stop;
+        int stage;
+    };
+    std::vector<Mark> marks;
+    double prof_ms[COUPLE_N_STAGES] = {0, 0, 0};
+    int prof_count[COUPLE_N_STAGES] = {0, 0, 0};
+};
+
+namespace couple {
+
+// LUT build (tables.hip)
+hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
+
+// strip kernels (strip.hip): Xi on the packed upper triangle.
+//   pol: also TE and EE.  l3 restricted to [l3_lo, l3_hi].
+hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
+                                const double* wpp, int n, hipStream_t s);
+hipError_t launch_strip(const couple_ctx* ctx, int lmax, bool pol, int precision, int l3_lo,
+                        int l3_hi, hipStream_t s);
+
+// fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
+//   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE) output i comes from, n_out outputs.
+hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
+                       double* out, hipStream_t s);
+hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
+                      const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
+// out[0 .. n) = 0 with a kernel (safe inside captured graphs)
+hipError_t launch_zero(double* out, size_t n, hipStream_t s);
+
+}  // namespace couple

@@ -1,0 +1,195 @@
+// From the packed upper triangle Xi(l1, l1 + d) to the output matrices.
+//
+// Xi is symmetric in (l1, l2); K is not: K_{l1 l2} = (2 l2 + 1) Xi(l1, l2)
+// (Sec. 2 eqs. K_TT, K_EE; App. A).  The paper fills the lower triangle from
+// the upper one (Sec. 4.1); here that is done on Xi, and each 64 x 64 tile
+// of K is written with its own column factor.
+//
+// fill: one work-group per upper tile pair (I <= J).  The tile of Xi is read
+// diagonal by diagonal (consecutive l1 are consecutive in memory), kept in
+// LDS, and written twice: K[l1][l2] row by row and the mirrored tile
+// K[l2][l1] = (2 l1 + 1) Xi(l1, l2), also row by row, so both halves are
+// coalesced.  K^BB is written from the same LDS values as K^EE.
+//
+// bin: K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2} per
+// (b, b') work-group, reduced in a fixed order.
+#include "couple_internal.hpp"
+
+namespace couple {
+namespace {
+
+constexpr int kT = 64;           // tile edge
+constexpr int kFillThreads = 256;
+
+struct FillArgs {
+    const double* xi;
+    long long xi_stride;
+    double* out;
+    long long out_stride;        // (lmax+1)^2
+    int lmax;
+    int dmax;                    // Xi exists for d <= dmax, 0 beyond
+    int n_tiles;                 // tiles per edge
+    int n_out;
+    int src[4];                  // Xi index of each output
+};
+
+__device__ inline void pair_from_index(int t, int n, int* I, int* J) {
+    // t enumerates (I, J), I <= J, row by row: row I holds n - I pairs
+    int i = 0;
+    int rem = t;
+    // closed form first guess, then correct
+    while (rem >= n - i) {
+        rem -= n - i;
+        ++i;
+    }
+    *I = i;
+    *J = i + rem;
+}
+
+__global__ void __launch_bounds__(kFillThreads)
+fill_kernel(FillArgs a) {
+    __shared__ double tile[kT][kT + 1];
+    int I, J;
+    pair_from_index(blockIdx.x, a.n_tiles, &I, &J);
+    const int r0 = kT * I, c0 = kT * J;
+    const int t = threadIdx.x;
+    int last_src = -1;
+
+    for (int o = 0; o < a.n_out; ++o) {
+        const int src = a.src[o];
+        if (src != last_src) {
+            __syncthreads();
+            const double* xi = a.xi + (long long)src * a.xi_stride;
+            // diagonals d = dj + dl - 63, dl = 0 .. 126; element (r, c = r + dl - 63)
+            for (int idx = t; idx < (2 * kT - 1) * kT; idx += kFillThreads) {
+                const int r = idx % kT;
+                const int dl = idx / kT;
+                const int c = r + dl - (kT - 1);
+                if (c < 0 || c >= kT) continue;
+                const int l1 = r0 + r, l2 = c0 + c;
+                if (l1 > a.lmax || l2 > a.lmax || l2 < l1) continue;
+                const int d = l2 - l1;
+                tile[r][c] = (d <= a.dmax) ? xi[diag_offset(a.lmax, d) + l1] : 0.0;
+            }
+            __syncthreads();
+            last_src = src;
+        }
+        double* out = a.out + (long long)o * a.out_stride;
+        const long long ld = a.lmax + 1;
+        if (I == J) {
+            for (int idx = t; idx < kT * kT; idx += kFillThreads) {
+                const int r = idx / kT, c = idx % kT;
+                const int l1 = r0 + r, l2 = c0 + c;
+                if (l1 > a.lmax || l2 > a.lmax) continue;
+                const double x = (c >= r) ? tile[r][c] : tile[c][r];
+                out[l1 * ld + l2] = (2.0 * l2 + 1.0) * x;
+            }
+        } else {
+            for (int idx = t; idx < kT * kT; idx += kFillThreads) {
+                const int r = idx / kT, c = idx % kT;
+                const int l1 = r0 + r, l2 = c0 + c;
+                if (l1 <= a.lmax && l2 <= a.lmax) out[l1 * ld + l2] = (2.0 * l2 + 1.0) * tile[r][c];
+            }
+            for (int idx = t; idx < kT * kT; idx += kFillThreads) {
+                const int c = idx / kT, r = idx % kT;
+                const int l1 = r0 + r, l2 = c0 + c;
+                if (l1 <= a.lmax && l2 <= a.lmax) out[l2 * ld + l1] = (2.0 * l1 + 1.0) * tile[r][c];
+            }
+        }
+    }
+}
+
+constexpr int kBinThreads = 256;
+
+struct BinArgs {
+    const double* xi;
+    long long xi_stride;
+    double* out;
+    const int* edges;            // device copy, n_bins + 1
+    int n_bins;
+    int lmax;
+    int dmax;
+    int n_out;
+    int src[4];
+};
+
+__global__ void __launch_bounds__(kBinThreads)
+bin_kernel(BinArgs a) {
+    __shared__ double red[kBinThreads];
+    const int bb = blockIdx.x / a.n_bins, bc = blockIdx.x % a.n_bins;
+    const int r_lo = a.edges[bb], r_hi = a.edges[bb + 1];
+    const int c_lo = a.edges[bc], c_hi = a.edges[bc + 1];
+    const int nr = r_hi - r_lo, ncl = c_hi - c_lo;
+    // smallest |l1 - l2| between the two bins
+    const int gap = (c_lo >= r_hi) ? c_lo - (r_hi - 1) : (r_lo >= c_hi ? r_lo - (c_hi - 1) : 0);
+    const int t = threadIdx.x;
+    for (int o = 0; o < a.n_out; ++o) {
+        const double* xi = a.xi + (long long)a.src[o] * a.xi_stride;
+        double acc = 0.0;
+        if (gap <= a.dmax) {
+            for (int idx = t; idx < nr * ncl; idx += kBinThreads) {
+                const int l1 = r_lo + idx / ncl, l2 = c_lo + idx % ncl;
+                const int lo = min(l1, l2), d = abs(l2 - l1);
+                if (d <= a.dmax) acc += (2.0 * l2 + 1.0) * xi[diag_offset(a.lmax, d) + lo];
+            }
+        }
+        red[t] = acc;
+        __syncthreads();
+        for (int w = kBinThreads / 2; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0)
+            a.out[((long long)o * a.n_bins + bb) * a.n_bins + bc] = red[0] / (double)nr;
+        __syncthreads();
+    }
+}
+
+__global__ void zero_kernel(double* __restrict__ out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_zero(double* out, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
+                       double* out, hipStream_t s) {
+    FillArgs a;
+    a.xi = ctx->xi;
+    a.xi_stride = tri_size(lmax);
+    a.out = out;
+    a.out_stride = (long long)(lmax + 1) * (lmax + 1);
+    a.lmax = lmax;
+    a.dmax = dmax;
+    a.n_tiles = (lmax + kT) / kT;
+    a.n_out = n_out;
+    for (int i = 0; i < 4; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
+    const long long n_pairs = (long long)a.n_tiles * (a.n_tiles + 1) / 2;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)n_pairs), dim3(kFillThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
+                      const int* bin_edges_dev, int n_bins, double* out, hipStream_t s) {
+    BinArgs a;
+    a.xi = ctx->xi;
+    a.xi_stride = tri_size(lmax);
+    a.out = out;
+    a.edges = bin_edges_dev;
+    a.n_bins = n_bins;
+    a.lmax = lmax;
+    a.dmax = dmax;
+    a.n_out = n_out;
+    for (int i = 0; i < 4; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
+    hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(n_bins * n_bins)), dim3(kBinThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace couple

@@ -1,0 +1,457 @@
+// The l3 reduction of the coupling kernels (Sec. 2 eqs. K_TT, K_EE; App. A)
+// on the packed upper triangle Xi(l1, l1 + d), d >= 0.
+//
+// Per term, with l2 = l1 + d and l3 = d + 2k (k = 0 .. l1: even L only, so
+// the parity projectors of App. A are structural), the halved triangle
+// combinations of eq. trianglecombos are p1 = d + k, p2 = k, p3 = l1 - k and
+// p = l1 + d + k.  From eq. 000_sq_main,
+//
+//     (l1 l2 l3; 0 0 0)^2 = g(p1) g(p2) g(p3) / ((2p+1) g(p))
+//                         = [g(k) g(d+k)] * [g(l1-k) * h(l1+d+k)],
+//
+// with h(p) = 1/((2p+1) g(p)).  The first factor depends on (d, k) only and
+// is folded, together with the scaled window W'_l3 = (2 l3 + 1) W_l3/(4 pi),
+// into per-step constants U_X(k) shared by a whole wavefront; the second is
+// a product of two table values that slide by one entry per step.
+//
+// The (-2 2 0) symbol.  The two-term closed form of App. B.3
+// (eq. 022_linear_closedform), applied with (j1, j2, j3) = (l3, l1, l2) --
+// the m = 0 column first, as the cyclic permutation of eq. permutation
+// requires -- expresses (l1 l2 l3; -2 2 0) through (l1 l2 l3; 0 0 0) and
+// (l1 l2+2 l3; 0 0 0).  The ratio of those two (0 0 0) symbols follows from
+// eq. 000_sq_main and eq. g_rec (the same step as App. B.5), and with it the
+// closed form collapses to a single multiple of the (0 0 0) symbol:
+//
+//     (l1 l2 l3; -2 2 0) = (l1 l2 l3; 0 0 0) * N' / (2 lambda eta),
+//     N' = u (u - 2) - 2 a b,   u = a + b - c,
+//     a = l1(l1+1), b = l2(l2+1), c = l3(l3+1),
+//     lambda eta = sqrt(a (a-2) b (b-2)) = 1/(c_l1 c_l2).
+//
+// N' is an integer; here it is evaluated as N' = c (c - 2(a+b-1)) + a(a-2) + b(b-2)
+// with one fused multiply-add, exact in float64 while |N'| < 2^53.  The
+// "(2,-2,0) recurrence" is thus an integer update of c along the strip.  The
+// three kernels then are
+//
+//     Xi_TT = sum_k U_TT(k) P,   Xi_TE = s sum_k U_TP(k) P N',
+//     Xi_EE = s^2 sum_k U_PP(k) P N'^2,     P = g(l1-k) h(l1+d+k),  s = c_l1 c_l2 / 2,
+//
+// and s = 0 for l1 < 2 or l2 < 2, where the (-2 2 0) symbol vanishes.
+//
+// Mapping.  One wavefront per work item (d, block of 64 R consecutive l1);
+// lane i owns l1 = A + R i + j, j < R, and walks k.  g(l1 - k) and
+// h(l1 + d + k) are kept in registers as windows of R values that slide by
+// one per step (one LDS read each per step for R terms); U_X(k) and c(k) are
+// read by the whole wave from one LDS address.  Terms with k > l1 read the
+// zero guard of the g window and vanish, so lanes of a wave share one trip
+// count.  Table windows are staged in LDS in chunks of kStripChunk steps
+// with one padding word per R entries (a lane stride of R+1 doubles is free
+// of bank conflicts).  Work items are numbered longest first.
+#include "couple_internal.hpp"
+
+namespace couple {
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;  // 1/(4 pi)
+
+__global__ void scale_windows_kernel(const double* __restrict__ wtt, const double* __restrict__ wtp,
+                                     const double* __restrict__ wpp, int n, int stride,
+                                     double* __restrict__ wp, float* __restrict__ wpf) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const double f = (2.0 * l + 1.0) * kInv4Pi;
+    const double a = wtt ? wtt[l] * f : 0.0;
+    const double b = wtp ? wtp[l] * f : 0.0;
+    const double c = wpp ? wpp[l] * f : 0.0;
+    wp[l] = a;
+    wp[stride + l] = b;
+    wp[2 * stride + l] = c;
+    wpf[l] = (float)a;
+    wpf[stride + l] = (float)b;
+    wpf[2 * stride + l] = (float)c;
+}
+
+struct StripArgs {
+    const double* g;     // g(p), index 0 = p 0, valid 0 .. lmax_max
+    const double* h;     // 1/((2p+1) g(p)), valid 0 .. 2 lmax_max
+    const double* wp;    // scaled windows, 3 x wp_stride
+    const double* cl;    // c_l
+    double* xi;          // 3 packed triangles of xi_stride
+    long long xi_stride;
+    int wp_stride;
+    int g_len, h_len;    // valid lengths of g and h
+    int lmax;
+    int dmax;            // largest diagonal computed
+    int bmax;            // largest l1 block index
+    int l3_lo, l3_hi;
+};
+
+template <int R>
+struct Win {
+    static constexpr int kB = kWave * R;                // l1 per item
+    static constexpr int kLen = kB + kStripChunk - 1;   // window length
+    static constexpr int kPhys = kLen + kLen / R + 1;   // with padding
+    __device__ static inline int phys(int slot) { return slot + slot / R; }
+};
+
+template <int R, bool POL>
+__global__ void __launch_bounds__(kWave)
+strip_fp64_kernel(StripArgs a) {
+    using W = Win<R>;
+    constexpr int B = W::kB;
+    constexpr int KC = kStripChunk;
+    __shared__ double s_g[W::kPhys];
+    __shared__ double s_h[W::kPhys];
+    __shared__ double4 s_u[KC];
+
+    // ---- work item: level b from bmax down, d ascending within a level ----
+    int item = blockIdx.x;
+    int b = a.bmax;
+    for (; b > 0; --b) {
+        const int nb = min(a.lmax - B * b, a.dmax) + 1;
+        if (nb > 0) {
+            if (item < nb) break;
+            item -= nb;
+        }
+    }
+    const int d = item;
+    const int A = B * b;
+    const int n_valid = a.lmax - d + 1;                  // l1 = 0 .. n_valid - 1
+    const int blk_max = min(A + B, n_valid) - 1;         // largest l1 in this block
+    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);     // ceil((l3_lo - d)/2)
+    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);   // floor((l3_hi - d)/2)
+
+    const int lane = threadIdx.x;
+    const int l1_0 = A + R * lane;
+
+    double tt[R], te[R], ee[R], gam2[R], kap[R], gw[R], hw[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        tt[j] = te[j] = ee[j] = 0.0;
+        const long long l1 = l1_0 + j, l2 = l1 + d;
+        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+        gam2[j] = (double)(2 * (aa + bb - 1));
+        kap[j] = (double)(aa * (aa - 2) + bb * (bb - 2));
+    }
+
+    const double* wtt = a.wp;
+    const double* wtp = a.wp + a.wp_stride;
+    const double* wpp = a.wp + 2 * a.wp_stride;
+
+    for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
+        const int kc = min(KC, k_hi - k0 + 1);
+        __syncthreads();
+        // stage g(e), e = A - k0 - KC + 1 + slot; h(e), e = A + d + k0 + slot
+        const int g_base = A - k0 - KC + 1;
+        const int h_base = A + d + k0;
+        for (int slot = lane; slot < W::kLen; slot += kWave) {
+            const int eg = g_base + slot, eh = h_base + slot;
+            s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
+            s_h[W::phys(slot)] = (eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
+        }
+        for (int s = lane; s < KC; s += kWave) {
+            double4 u = {0.0, 0.0, 0.0, 0.0};
+            if (s < kc) {
+                const int k = k0 + s;
+                const int l3 = d + 2 * k;
+                const double gg = a.g[k] * a.g[d + k];
+                u.x = wtt[l3] * gg;
+                if (POL) {
+                    u.y = wtp[l3] * gg;
+                    u.z = wpp[l3] * gg;
+                    u.w = (double)((long long)l3 * (l3 + 1));
+                }
+            }
+            s_u[s] = u;
+        }
+        __syncthreads();
+
+        if (k0 == k_lo) {
+            // windows as they stand one step before k_lo: every step below
+            // first slides them by one and then reads the new entry
+#pragma unroll
+            for (int j = 0; j < R - 1; ++j) gw[j] = s_g[W::phys(R * lane + j + KC)];
+            gw[R - 1] = 0.0;
+            hw[0] = 0.0;
+#pragma unroll
+            for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
+        }
+        // steps are taken in groups of R; the staged U of steps past kc is 0
+        const int kc_r = (kc + R - 1) / R * R;
+        for (int s0 = 0; s0 < kc_r; s0 += R) {
+            // phys(R lane + KC - 1 - s) and phys(R lane + R - 1 + s) for s = s0 + u
+            const double* pg = s_g + (R + 1) * (lane + (KC - s0) / R - 1) + (R - 1);
+            const double* ph = s_h + (R + 1) * (lane + s0 / R) + (R - 1);
+            const double4* pu = s_u + s0;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+#pragma unroll
+                for (int j = R - 1; j > 0; --j) gw[j] = gw[j - 1];
+                gw[0] = pg[-u];
+#pragma unroll
+                for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
+                hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
+                const double4 uu = pu[u];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const double P = gw[j] * hw[j];
+                    tt[j] = __builtin_fma(uu.x, P, tt[j]);
+                    if (POL) {
+                        const double dc = uu.w - gam2[j];
+                        const double N = __builtin_fma(uu.w, dc, kap[j]);
+                        const double y = P * N;
+                        te[j] = __builtin_fma(uu.y, y, te[j]);
+                        const double z = y * N;
+                        ee[j] = __builtin_fma(uu.z, z, ee[j]);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- store Xi on the packed triangle ----
+    const long long off = diag_offset(a.lmax, d);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int l1 = l1_0 + j;
+        if (l1 < n_valid) {
+            a.xi[off + l1] = tt[j];
+            if (POL) {
+                const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
+                a.xi[a.xi_stride + off + l1] = s * te[j];
+                a.xi[2 * a.xi_stride + off + l1] = (s * s) * ee[j];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32-compensated variant.  Same mapping and staging as strip_fp64_kernel;
+// the terms are float32:
+//   P = g(l1-k) h(l1+d+k) from float32 tables (each rounded once from the
+//       double-double build),
+//   U_X(k) formed in float64 from the float64 tables and windows and rounded
+//       once to float32,
+//   N' = t^2 - (2ab + 1) with t = c - (a + b - 1) taken exactly in int32 and
+//       rounded once to float32 (the subtraction cancels, so it must not be
+//       done in float32), then one fused multiply-add.
+// Accumulation: each lane sums kCompBlock consecutive terms with float32 FMA
+// and adds the block sum into a Kahan (sum, compensation) pair in float32;
+// the pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.
+constexpr int kCompBlock = 2 * kStripR;
+
+template <int R, bool POL>
+__global__ void __launch_bounds__(kWave)
+strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
+    using W = Win<R>;
+    constexpr int B = W::kB;
+    constexpr int KC = kStripChunk;
+    constexpr int G = kCompBlock;
+    static_assert(KC % G == 0 && G % R == 0, "chunk must hold whole blocks");
+    __shared__ float s_g[W::kPhys];
+    __shared__ float s_h[W::kPhys];
+    __shared__ float4 s_u[KC];
+
+    int item = blockIdx.x;
+    int b = a.bmax;
+    for (; b > 0; --b) {
+        const int nb = min(a.lmax - B * b, a.dmax) + 1;
+        if (nb > 0) {
+            if (item < nb) break;
+            item -= nb;
+        }
+    }
+    const int d = item;
+    const int A = B * b;
+    const int n_valid = a.lmax - d + 1;
+    const int blk_max = min(A + B, n_valid) - 1;
+    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+
+    const int lane = threadIdx.x;
+    const int l1_0 = A + R * lane;
+
+    // Kahan pairs (sum, compensation) per spectrum and lane-owned l1
+    float kt[R], kte[R], kee[R], ct[R], cte[R], cee[R];
+    float gw[R], hw[R], beta[R];
+    int gam[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        kt[j] = kte[j] = kee[j] = ct[j] = cte[j] = cee[j] = 0.0f;
+        const long long l1 = l1_0 + j, l2 = l1 + d;
+        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+        gam[j] = (int)(aa + bb - 1);
+        beta[j] = (float)(2.0 * (double)aa * (double)bb + 1.0);
+    }
+
+    const double* wtt = a.wp;
+    const double* wtp = a.wp + a.wp_stride;
+    const double* wpp = a.wp + 2 * a.wp_stride;
+
+    for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
+        const int kc = min(KC, k_hi - k0 + 1);
+        __syncthreads();
+        const int g_base = A - k0 - KC + 1;
+        const int h_base = A + d + k0;
+        for (int slot = lane; slot < W::kLen; slot += kWave) {
+            const int eg = g_base + slot, eh = h_base + slot;
+            s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? gf[eg] : 0.0f;
+            s_h[W::phys(slot)] = (eh >= 0 && eh < a.h_len) ? hf[eh] : 0.0f;
+        }
+        for (int s = lane; s < KC; s += kWave) {
+            float4 u = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (s < kc) {
+                const int k = k0 + s;
+                const int l3 = d + 2 * k;
+                const double gg = a.g[k] * a.g[d + k];
+                u.x = (float)(wtt[l3] * gg);
+                if (POL) {
+                    u.y = (float)(wtp[l3] * gg);
+                    u.z = (float)(wpp[l3] * gg);
+                    u.w = __int_as_float(l3 * (l3 + 1));
+                }
+            }
+            s_u[s] = u;
+        }
+        __syncthreads();
+
+        if (k0 == k_lo) {
+#pragma unroll
+            for (int j = 0; j < R - 1; ++j) gw[j] = s_g[W::phys(R * lane + j + KC)];
+            gw[R - 1] = 0.0f;
+            hw[0] = 0.0f;
+#pragma unroll
+            for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
+        }
+        const int kc_r = (kc + G - 1) / G * G;
+        for (int sb = 0; sb < kc_r; sb += G) {
+            float bt[R], bte[R], bee[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) bt[j] = bte[j] = bee[j] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < G / R; ++q) {
+                const int s0 = sb + q * R;
+                const float* pg = s_g + (R + 1) * (lane + (KC - s0) / R - 1) + (R - 1);
+                const float* ph = s_h + (R + 1) * (lane + s0 / R) + (R - 1);
+                const float4* pu = s_u + s0;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+#pragma unroll
+                    for (int j = R - 1; j > 0; --j) gw[j] = gw[j - 1];
+                    gw[0] = pg[-u];
+#pragma unroll
+                    for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
+                    hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
+                    const float4 uu = pu[u];
+                    const int c = __float_as_int(uu.w);
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float P = gw[j] * hw[j];
+                        bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
+                        if (POL) {
+                            const float t = (float)(c - gam[j]);
+                            const float N = __builtin_fmaf(t, t, -beta[j]);
+                            const float y = P * N;
+                            bte[j] = __builtin_fmaf(uu.y, y, bte[j]);
+                            const float z = y * N;
+                            bee[j] = __builtin_fmaf(uu.z, z, bee[j]);
+                        }
+                    }
+                }
+            }
+            // Kahan step: add the block sums
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                {
+                    const float yv = bt[j] - ct[j];
+                    const float tv = kt[j] + yv;
+                    ct[j] = (tv - kt[j]) - yv;
+                    kt[j] = tv;
+                }
+                if (POL) {
+                    const float yv = bte[j] - cte[j];
+                    const float tv = kte[j] + yv;
+                    cte[j] = (tv - kte[j]) - yv;
+                    kte[j] = tv;
+                    const float yw = bee[j] - cee[j];
+                    const float tw = kee[j] + yw;
+                    cee[j] = (tw - kee[j]) - yw;
+                    kee[j] = tw;
+                }
+            }
+        }
+    }
+
+    const long long off = diag_offset(a.lmax, d);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int l1 = l1_0 + j;
+        if (l1 < n_valid) {
+            a.xi[off + l1] = (double)kt[j] - (double)ct[j];
+            if (POL) {
+                const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
+                a.xi[a.xi_stride + off + l1] = s * ((double)kte[j] - (double)cte[j]);
+                a.xi[2 * a.xi_stride + off + l1] = (s * s) * ((double)kee[j] - (double)cee[j]);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
+                                const double* wpp, int n, hipStream_t s) {
+    const int stride = 2 * ctx->lmax_max + 1;
+    hipLaunchKernelGGL(scale_windows_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wtt, wtp, wpp, n,
+                       stride, ctx->wp, ctx->wpf);
+    return hipGetLastError();
+}
+
+static long long count_items(int lmax, int dmax, int B, int* bmax_out) {
+    const int bmax = lmax / B;
+    long long total = 0;
+    for (int b = bmax; b >= 0; --b) {
+        const int nb = std::min(lmax - B * b, dmax) + 1;
+        if (nb > 0) total += nb;
+    }
+    *bmax_out = bmax;
+    return total;
+}
+
+hipError_t launch_strip(const couple_ctx* ctx, int lmax, bool pol, int precision, int l3_lo, int l3_hi,
+                        hipStream_t s) {
+    constexpr int R = kStripR;
+    StripArgs a;
+    a.g = ctx->g_pad + kTablePad;
+    a.h = ctx->h_pad + kTablePad;
+    a.wp = ctx->wp;
+    a.cl = ctx->cl;
+    a.xi = ctx->xi;
+    a.xi_stride = tri_size(lmax);
+    a.wp_stride = 2 * ctx->lmax_max + 1;
+    a.g_len = ctx->lmax_max + 1;
+    a.h_len = 2 * ctx->lmax_max + 1;
+    a.lmax = lmax;
+    a.dmax = std::min(lmax, l3_hi);
+    a.l3_lo = l3_lo;
+    a.l3_hi = l3_hi;
+    const long long n_items = count_items(lmax, a.dmax, kWave * R, &a.bmax);
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_items), block(kWave);
+    if (precision == COUPLE_FP32C) {
+        const float* gf = ctx->gf_pad + kTablePad;
+        const float* hf = ctx->hf_pad + kTablePad;
+        if (pol)
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, true>), grid, block, 0, s, a, gf, hf);
+        else
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, false>), grid, block, 0, s, a, gf, hf);
+    } else {
+        if (pol)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((strip_fp64_kernel<R, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace couple

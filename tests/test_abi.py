@@ -1,0 +1,80 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/couple.h declares, rejects bad arguments that need no device, and
+neither links nor names the oracle.  No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "couple.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(couple_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2602_15605_amd import couple
+    if not os.path.exists(couple.LIB_PATH):
+        from paper_2602_15605_amd import build
+        build.build()
+    return couple.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ("couple_init", "couple_matrix", "couple_band", "couple_free", "couple_last_error",
+              "couple_tables", "couple_lmax_max"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2602_15605_amd import couple
+    out = subprocess.run(["nm", "-D", "--defined-only", couple.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for name in _declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_library_does_not_touch_the_oracle():
+    from paper_2602_15605_amd import couple
+    syms = subprocess.run(["nm", "-D", couple.LIB_PATH], check=True, capture_output=True, text=True).stdout
+    assert "oracle" not in syms
+    deps = subprocess.run(["readelf", "-d", couple.LIB_PATH], check=True, capture_output=True, text=True).stdout
+    assert "oracle" not in deps
+    for fn in os.listdir(os.path.join(ROOT, "paper_2602_15605_amd")):
+        if fn.endswith(".py"):
+            src = open(os.path.join(ROOT, "paper_2602_15605_amd", fn)).read()
+            assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+def test_host_side_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.couple_init(-1, ctypes.byref(h)) == -1
+    assert "lmax_max" in lib.couple_last_error(None).decode()
+    assert lib.couple_init(16385, ctypes.byref(h)) == -1
+    assert lib.couple_init(10, None) == -1
+    assert lib.couple_matrix(None, None, None, None, 0, 0, 1, 0, None, None) == -1
+    assert lib.couple_band(None, 0, 1, None, None, None, 0, 0, 1, 0, None, 0, None, None) == -1
+    assert lib.couple_tables(None, None, None, None, None, None) == -1
+    assert lib.couple_lmax_max(None) == -1
+    lib.couple_free(None)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    from paper_2602_15605_amd import couple
+    saved = couple._lib
+    try:
+        couple._lib = None
+        with pytest.raises(couple.CoupleError):
+            couple.load_library(str(tmp_path / "missing.so"))
+    finally:
+        couple._lib = saved
