@@ -125,6 +125,22 @@ int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const
                 const int *bin_edges, int n_bins, double *out, void *stream);
 
 /*
+ * couple_band_batched -- couple_band for n_masks windows in one call (the
+ * per-mask work is enqueued back to back on `stream`).
+ *   W_TT, W_TP, W_PP : HOST arrays of n_masks DEVICE pointers (an array may
+ *                      be NULL when no requested spectrum uses it).
+ *   out              : device float64, n_masks consecutive outputs of the
+ *                      couple_band layout (mask-major).
+ *   other arguments as couple_band; every mask shares lmax, band and bins.
+ * Errors: as couple_band (the message names the offending mask), EINVAL for
+ * n_masks < 1.
+ */
+int couple_band_batched(couple_ctx *ctx, int n_masks, int l3_lo, int l3_hi, const double *const *W_TT,
+                        const double *const *W_TP, const double *const *W_PP, int w_len, int lmax,
+                        unsigned spectra, int precision, const int *bin_edges, int n_bins, double *out,
+                        void *stream);
+
+/*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for
  * inspection and tests).  Any pointer may be NULL to skip that table.
  *   g    : lmax_max + 1 float64,   g[p] = g(p)                  (eq. gdef)

@@ -45,6 +45,11 @@ def _load():
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.oracle_coupling_rows.restype = ctypes.c_int
+        lib.oracle_band_rows.argtypes = lib.oracle_coupling_rows.argtypes
+        lib.oracle_band_rows.restype = ctypes.c_int
+        lib.oracle_threej_row_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_threej_row_forward.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -59,6 +64,20 @@ def threej_row(l1: int, l2: int, m: int) -> np.ndarray:
     return out
 
 
+def threej_row_forward(l1: int, l2: int, m: int, l3_hi: int) -> np.ndarray:
+    """(l1 l2 l3; m -m 0) for l3 = |l1-l2| .. min(l1+l2, l3_hi), by the forward
+    recursion from the exact single-term value at the lower end."""
+    jmin = abs(l1 - l2)
+    n = min(l1 + l2, l3_hi) - jmin + 1
+    if n <= 0:
+        return np.zeros(0)
+    out = np.zeros(n, dtype=np.float64)
+    rc = _load().oracle_threej_row_forward(int(l1), int(l2), int(m), int(l3_hi), out.ctypes.data, n)
+    if rc != n:
+        raise RuntimeError("oracle_threej_row_forward failed (%d)" % rc)
+    return out
+
+
 def _as_f64(w):
     if w is None:
         return None
@@ -66,12 +85,14 @@ def _as_f64(w):
 
 
 def coupling_rows(lmax, W_TT=None, W_TP=None, W_PP=None, rows=None, spectra=("TT",),
-                  l3_range=None, n_threads=0, with_abs=True):
+                  l3_range=None, n_threads=0, with_abs=True, band_forward=False):
     """K rows (and the |term| sums) for the requested l1 rows and spectra.
 
     Returns ``(K, A)`` with shapes [len(spectra), len(rows), lmax+1]; spectra
     are returned in the order given.  ``l3_range=(lo, hi)`` restricts the l3
-    sum (band-limited kernels).
+    sum (band-limited kernels).  ``band_forward`` builds each row only up to
+    l3 = hi by the forward recursion from its exact lower end (cost O(hi) per
+    element instead of O(l1 + l2)); it requires ``l3_range``.
     """
     spectra = tuple(spectra)
     bits = 0
@@ -85,7 +106,10 @@ def coupling_rows(lmax, W_TT=None, W_TP=None, W_PP=None, rows=None, spectra=("TT
     K = np.zeros((len(order), len(rows), lmax + 1), dtype=np.float64)
     A = np.zeros_like(K) if with_abs else None
     ptr = [w.ctypes.data if w is not None else None for w in ws]
-    rc = _load().oracle_coupling_rows(int(lmax), ptr[0], ptr[1], ptr[2], int(w_len), lo, hi,
+    fn = _load().oracle_band_rows if band_forward else _load().oracle_coupling_rows
+    if band_forward and l3_range is None:
+        raise ValueError("band_forward needs l3_range")
+    rc = fn(int(lmax), ptr[0], ptr[1], ptr[2], int(w_len), lo, hi,
                                       rows.ctypes.data, len(rows), bits, K.ctypes.data,
                                       A.ctypes.data if A is not None else None, int(n_threads))
     if rc != 0:

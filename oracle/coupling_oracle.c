@@ -263,3 +263,176 @@ int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const
     }
     return err ? -2 : 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Band-limited rows (Sec. 4.3): only l3 <= l3_hi enters the sum, so the row
+ * is needed from its lower end jmin = |l1 - l2| up to min(jmax, l3_hi) only.
+ * The row is started at jmin with the exact value of the Racah sum there --
+ * at the lower end the sum has a single term, evaluated here in log form with
+ * lgammal -- and continued upwards by the same Schulten--Gordon recursion
+ * (forward is the stable direction out of the lower end).  No normalisation
+ * is needed: the seed carries the absolute scale.
+ */
+
+/* log|term| and sign of the single-term Racah sum of (j1 j2 j3; m1 m2 m3), or
+ * 0 if the sum does not have exactly one term. */
+static int racah_single_term(long j1, long j2, long j3, long m1, long m2, long m3, ld *logabs, int *sign)
+{
+    long t_lo = 0, t_hi, t;
+    ld lg;
+    if (j2 - j3 - m1 > t_lo) t_lo = j2 - j3 - m1;
+    if (j1 - j3 + m2 > t_lo) t_lo = j1 - j3 + m2;
+    t_hi = j1 + j2 - j3;
+    if (j1 - m1 < t_hi) t_hi = j1 - m1;
+    if (j2 + m2 < t_hi) t_hi = j2 + m2;
+    if (t_lo != t_hi) return 0;
+    t = t_lo;
+    /* sqrt(Delta) sqrt(prod (j +- m)!) / denominator factorials */
+    lg = 0.5L * (lgammal((ld)(j1 + j2 - j3 + 1)) + lgammal((ld)(j1 - j2 + j3 + 1)) +
+                 lgammal((ld)(-j1 + j2 + j3 + 1)) - lgammal((ld)(j1 + j2 + j3 + 2)));
+    lg += 0.5L * (lgammal((ld)(j1 + m1 + 1)) + lgammal((ld)(j1 - m1 + 1)) + lgammal((ld)(j2 + m2 + 1)) +
+                  lgammal((ld)(j2 - m2 + 1)) + lgammal((ld)(j3 + m3 + 1)) + lgammal((ld)(j3 - m3 + 1)));
+    lg -= lgammal((ld)(t + 1)) + lgammal((ld)(j3 - j2 + t + m1 + 1)) + lgammal((ld)(j3 - j1 + t - m2 + 1)) +
+          lgammal((ld)(j1 + j2 - j3 - t + 1)) + lgammal((ld)(j1 - t - m1 + 1)) + lgammal((ld)(j2 - t + m2 + 1));
+    *logabs = lg;
+    *sign = (((j1 - j2 - m3 + t) % 2) != 0) ? -1 : 1;
+    return 1;
+}
+
+/* f[i] = (l1 l2 jmin+i; m -m 0) for i = 0 .. n_out-1 (n_out <= row length). */
+static void sg_row_forward(int l1, int l2, int m, long n_out, ld *f)
+{
+    const long jmin = labs((long)l1 - l2);
+    const long d = (long)l1 - l2, s = (long)l1 + l2 + 1;
+    long i;
+    ld logabs = 0.0L, prev = 0.0L, cur, p_j = 0.0L;
+    int sign = 1;
+    if (n_out <= 0) return;
+    if (abs(m) > l1 || abs(m) > l2) {
+        for (i = 0; i < n_out; ++i) f[i] = 0.0L;
+        return;
+    }
+    /* the symbol with the l3 = jmin column first: (jmin l1 l2; 0 m -m) */
+    if (!racah_single_term(jmin, l1, l2, 0, m, -m, &logabs, &sign)) {
+        for (i = 0; i < n_out; ++i) f[i] = 0.0L; /* not reached for valid rows */
+        return;
+    }
+    cur = (ld)sign * expl(logabs);
+    f[0] = cur;
+    for (i = 0; i + 1 < n_out; ++i) {
+        const long j = jmin + i;
+        const ld p_j1 = sg_p(j + 1, d, s);
+        const ld nxt = -(-2.0L * (ld)m * (ld)(2 * j + 1) * cur + p_j * prev) / p_j1;
+        f[i + 1] = nxt;
+        prev = cur;
+        cur = nxt;
+        p_j = p_j1;
+    }
+}
+
+/* (l1 l2 l3; m -m 0) for l3 = |l1-l2| .. min(l1+l2, l3_hi) by the forward
+ * recursion from the exact lower end; returns the number written. */
+int oracle_threej_row_forward(int l1, int l2, int m, int l3_hi, double *out, int n_out)
+{
+    long jmin, n, i;
+    ld *buf;
+    if (l1 < 0 || l2 < 0 || !out) return -1;
+    jmin = labs((long)l1 - l2);
+    n = ((long)l1 + l2 < l3_hi ? (long)l1 + l2 : l3_hi) - jmin + 1;
+    if (n <= 0) return 0;
+    if (n_out < n) return -1;
+    buf = (ld *)malloc(sizeof(ld) * (size_t)n);
+    if (!buf) return -2;
+    sg_row_forward(l1, l2, m, n, buf);
+    for (i = 0; i < n; ++i) out[i] = (double)buf[i];
+    free(buf);
+    return (int)n;
+}
+
+/*
+ * Band-limited K rows: as oracle_coupling_rows with the l3 sum restricted to
+ * [l3_lo, l3_hi], but only the l2 with |l1 - l2| <= l3_hi are evaluated (the
+ * others have no l3 in the band: their K is exactly 0) and every row is built
+ * by the forward recursion up to l3_hi.
+ */
+int oracle_band_rows(int lmax, const double *W_TT, const double *W_TP, const double *W_PP, int w_len,
+                     int l3_lo, int l3_hi, const int *rows, int n_rows, unsigned spectra,
+                     double *K_out, double *A_out, int n_threads)
+{
+    const int n_sel = popcount5(spectra & 31u);
+    const long ncol = (long)lmax + 1;
+    const int need_pol = (spectra & (ORACLE_TE | ORACLE_EE | ORACLE_BB | ORACLE_EB)) != 0;
+    int r, err = 0;
+    if (lmax < 0 || n_rows < 0 || !rows || !K_out || n_sel == 0 || l3_lo < 0 || l3_hi < l3_lo) return -1;
+    if (w_len < (l3_hi < 2 * lmax ? l3_hi : 2 * lmax) + 1) return -1;
+    if ((spectra & ORACLE_TT) && !W_TT) return -1;
+    if ((spectra & ORACLE_TE) && !W_TP) return -1;
+    if ((spectra & (ORACLE_EE | ORACLE_BB | ORACLE_EB)) && !W_PP) return -1;
+    for (r = 0; r < n_rows; ++r)
+        if (rows[r] < 0 || rows[r] > lmax) return -1;
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+    memset(K_out, 0, sizeof(double) * (size_t)n_sel * n_rows * ncol);
+    if (A_out) memset(A_out, 0, sizeof(double) * (size_t)n_sel * n_rows * ncol);
+
+#pragma omp parallel reduction(| : err)
+    {
+        const long len = (long)l3_hi + 2;
+        ld *x = (ld *)malloc(sizeof(ld) * (size_t)len);
+        ld *z = (ld *)malloc(sizeof(ld) * (size_t)len);
+        long task;
+        if (!x || !z) err |= 1;
+#pragma omp for schedule(dynamic, 4)
+        for (task = 0; task < (long)n_rows * ncol; ++task) {
+            const int l1 = rows[task / ncol];
+            const int l2 = (int)(task % ncol);
+            const long ri = task / ncol;
+            const long jmin = labs((long)l1 - l2);
+            const long jtop = ((long)l1 + l2 < l3_hi) ? (long)l1 + l2 : l3_hi;
+            const long n = jtop - jmin + 1;
+            long i;
+            ld acc[5] = {0, 0, 0, 0, 0}, aab[5] = {0, 0, 0, 0, 0};
+            ld pref;
+            int k, o;
+            if (err || n <= 0) continue;
+            sg_row_forward(l1, l2, 0, n, x);
+            if (need_pol) sg_row_forward(l1, l2, -2, n, z);
+            for (i = 0; i < n; ++i) {
+                const long l3 = jmin + i;
+                const ld w3 = (ld)(2 * l3 + 1);
+                const int even = ((l1 + l2 + l3) & 1L) == 0;
+                ld t;
+                if (l3 < l3_lo) continue;
+                if (spectra & ORACLE_TT) {
+                    t = w3 * (ld)W_TT[l3] * x[i] * x[i];
+                    acc[0] += t; aab[0] += fabsl(t);
+                }
+                if ((spectra & ORACLE_TE) && even) {
+                    t = w3 * (ld)W_TP[l3] * x[i] * z[i];
+                    acc[1] += t; aab[1] += fabsl(t);
+                }
+                if ((spectra & ORACLE_EE) && even) {
+                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+                    acc[2] += t; aab[2] += fabsl(t);
+                }
+                if ((spectra & ORACLE_BB) && even) {
+                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+                    acc[3] += t; aab[3] += fabsl(t);
+                }
+                if ((spectra & ORACLE_EB) && !even) {
+                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+                    acc[4] += t; aab[4] += fabsl(t);
+                }
+            }
+            pref = (ld)(2 * l2 + 1) / (4.0L * PI_L);
+            for (k = 0, o = 0; k < 5; ++k) {
+                if (!(spectra & (1u << k))) continue;
+                K_out[((long)o * n_rows + ri) * ncol + l2] = (double)(pref * acc[k]);
+                if (A_out) A_out[((long)o * n_rows + ri) * ncol + l2] = (double)(pref * aab[k]);
+                ++o;
+            }
+        }
+        free(x);
+        free(z);
+    }
+    return err ? -2 : 0;
+}

@@ -55,6 +55,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_matrix.restype = i
     lib.couple_band.argtypes = [vp, i, i, dp, dp, dp, i, i, u, i, vp, i, dp, vp]
     lib.couple_band.restype = i
+    lib.couple_band_batched.argtypes = [vp, i, i, i, vp, vp, vp, i, i, u, i, vp, i, dp, vp]
+    lib.couple_band_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
     lib.couple_profile.argtypes = [vp, i]
@@ -185,6 +187,44 @@ def couple_band(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT", "EE", 
                                     PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision),
                                     edges.ctypes.data if edges is not None else None, n_bins,
                                     _dev_ptr(out, "out"), _stream_handle(stream))
+    _check(rc, ctx)
+    return out
+
+
+def _ptr_array(tensors, name):
+    if tensors is None:
+        return None, None
+    arr = (ctypes.c_void_p * len(tensors))(*[_dev_ptr(t, name) for t in tensors])
+    return arr, len(tensors)
+
+
+def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT", "EE", "BB"),
+                        precision="fp64", bin_edges=None, out=None, stream=None):
+    """couple_band for a list of masks: ``W_*`` are lists of GPU tensors (or None).
+
+    Returns [n_masks, n_spec, ...] with the couple_band layout per mask.
+    """
+    import torch
+    bits = _spectra_bits(spectra)
+    ns = _n_spec(bits)
+    lists = [W_TT, W_TP, W_PP]
+    n_masks = next(len(w) for w in lists if w is not None)
+    edges = None
+    n_bins = 0
+    if bin_edges is not None:
+        edges = np.ascontiguousarray(np.asarray(bin_edges, dtype=np.int32))
+        n_bins = len(edges) - 1
+    shape = (n_masks, max(ns, 1)) + ((n_bins, n_bins) if edges is not None else (lmax + 1, lmax + 1))
+    if out is None:
+        dev = next(w[0].device for w in lists if w is not None)
+        out = torch.empty(shape, dtype=torch.float64, device=dev)
+    arrs = [_ptr_array(w, n)[0] for w, n in zip(lists, ("W_TT", "W_TP", "W_PP"))]
+    w_len = min(int(t.numel()) for w in lists if w is not None for t in w)
+    rc = load_library().couple_band_batched(
+        ctx.handle, n_masks, int(l3_lo), int(l3_hi), *[ctypes.cast(a, ctypes.c_void_p) if a is not None else None
+                                                        for a in arrs],
+        w_len, int(lmax), bits, PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision),
+        edges.ctypes.data if edges is not None else None, n_bins, _dev_ptr(out, "out"), _stream_handle(stream))
     _check(rc, ctx)
     return out
 

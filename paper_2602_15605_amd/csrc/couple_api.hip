@@ -228,15 +228,13 @@ int couple_matrix(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     return COUPLE_OK;
 }
 
-int couple_band(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP,
-                const double* W_PP, int w_len, int lmax, unsigned spectra, int precision, const int* bin_edges,
-                int n_bins, double* out, void* stream) {
-    if (!ctx) return COUPLE_EINVAL;
-    ctx->err.clear();
-    int rc = check_common(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, out);
-    if (rc) return rc;
-    if (l3_lo < 0 || l3_hi < l3_lo)
-        return fail(ctx, COUPLE_EINVAL, "bad l3 band [%d, %d]", l3_lo, l3_hi);
+}  // extern "C"
+
+namespace {
+
+// Checks of couple_band / couple_band_batched beyond check_common.
+int check_band(couple_ctx* ctx, int l3_lo, int l3_hi, int w_len, int lmax, const int* bin_edges, int n_bins) {
+    if (l3_lo < 0 || l3_hi < l3_lo) return fail(ctx, COUPLE_EINVAL, "bad l3 band [%d, %d]", l3_lo, l3_hi);
     const int hi = std::min(l3_hi, 2 * lmax);
     if (w_len < hi + 1) return fail(ctx, COUPLE_EINVAL, "w_len=%d < %d", w_len, hi + 1);
     if (bin_edges) {
@@ -248,40 +246,101 @@ int couple_band(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const
             if (bin_edges[b + 1] <= bin_edges[b])
                 return fail(ctx, COUPLE_EINVAL, "bin edges must be strictly increasing (at %d)", b);
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return COUPLE_OK;
+}
+
+int upload_edges(couple_ctx* ctx, const int* bin_edges, int n_bins, hipStream_t s) {
+    // stage through pinned memory; wait for any earlier upload still reading it
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream sync before edge upload");
+    std::memcpy(ctx->edges_host, bin_edges, (n_bins + 1) * sizeof(int));
+    e = hipMemcpyAsync(ctx->edges_dev, ctx->edges_host, (n_bins + 1) * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "edge upload");
+    return COUPLE_OK;
+}
+
+// One mask of a band-limited call, edges (if any) already on the device.
+int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP, const double* W_PP,
+             int lmax, unsigned spectra, int precision, bool binned, int n_bins, double* out, hipStream_t s) {
     int src[4];
     const int n_out = output_sources(spectra, src);
+    const int hi = std::min(l3_hi, 2 * lmax);
     const int dmax = std::min(lmax, hi);
-    if (l3_lo <= hi) {
-        rc = run_reduction(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, l3_lo, hi, s);
-        if (rc) return rc;
-    }
     hipError_t e;
     if (l3_lo > hi) {
         // empty band: every element is 0
-        const size_t n = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
+        const size_t n = binned ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
         e = couple::launch_zero(out, n, s);
         if (e != hipSuccess) return hip_fail(ctx, e, "zero fill launch");
         return COUPLE_OK;
     }
+    int rc = run_reduction(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, l3_lo, hi, s);
+    if (rc) return rc;
+    {
+        Timed t(ctx, s, 2);
+        e = binned ? couple::launch_bin(ctx, lmax, dmax, src, n_out, ctx->edges_dev, n_bins, out, s)
+                   : couple::launch_fill(ctx, lmax, dmax, src, n_out, out, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, binned ? "bin launch" : "fill launch");
+    return COUPLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int couple_band(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP,
+                const double* W_PP, int w_len, int lmax, unsigned spectra, int precision, const int* bin_edges,
+                int n_bins, double* out, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    int rc = check_common(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, out);
+    if (rc) return rc;
+    rc = check_band(ctx, l3_lo, l3_hi, w_len, lmax, bin_edges, n_bins);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     if (bin_edges) {
-        // stage the edges through pinned memory; the copy is ordered on s
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(ctx, e, "stream sync before edge upload");
-        std::memcpy(ctx->edges_host, bin_edges, (n_bins + 1) * sizeof(int));
-        e = hipMemcpyAsync(ctx->edges_dev, ctx->edges_host, (n_bins + 1) * sizeof(int), hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return hip_fail(ctx, e, "edge upload");
-        {
-            Timed t(ctx, s, 2);
-            e = couple::launch_bin(ctx, lmax, dmax, src, n_out, ctx->edges_dev, n_bins, out, s);
+        rc = upload_edges(ctx, bin_edges, n_bins, s);
+        if (rc) return rc;
+    }
+    return band_one(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra, precision, bin_edges != nullptr, n_bins,
+                    out, s);
+}
+
+int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
+                        const double* const* W_TP, const double* const* W_PP, int w_len, int lmax,
+                        unsigned spectra, int precision, const int* bin_edges, int n_bins, double* out,
+                        void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (n_masks < 1) return fail(ctx, COUPLE_EINVAL, "n_masks=%d < 1", n_masks);
+    const bool need_tt = spectra & COUPLE_TT, need_tp = spectra & COUPLE_TE,
+               need_pp = spectra & (COUPLE_EE | COUPLE_BB);
+    if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
+        return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
+    for (int m = 0; m < n_masks; ++m) {
+        int rc = check_common(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
+                              need_pp ? W_PP[m] : nullptr, lmax, spectra, precision, out);
+        if (rc) {
+            ctx->err = "mask " + std::to_string(m) + ": " + ctx->err;
+            return rc;
         }
-        if (e != hipSuccess) return hip_fail(ctx, e, "bin launch");
-    } else {
-        {
-            Timed t(ctx, s, 2);
-            e = couple::launch_fill(ctx, lmax, dmax, src, n_out, out, s);
-        }
-        if (e != hipSuccess) return hip_fail(ctx, e, "fill launch");
+    }
+    int rc = check_band(ctx, l3_lo, l3_hi, w_len, lmax, bin_edges, n_bins);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (bin_edges) {
+        rc = upload_edges(ctx, bin_edges, n_bins, s);
+        if (rc) return rc;
+    }
+    int src[4];
+    const int n_out = output_sources(spectra, src);
+    const size_t per_mask = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
+    for (int m = 0; m < n_masks; ++m) {
+        rc = band_one(ctx, l3_lo, l3_hi, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
+                      need_pp ? W_PP[m] : nullptr, lmax, spectra, precision, bin_edges != nullptr, n_bins,
+                      out + m * per_mask, s);
+        if (rc) return rc;
     }
     return COUPLE_OK;
 }

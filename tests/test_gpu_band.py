@@ -1,0 +1,110 @@
+"""Band-limited coupling matrices (Sec. 4.3) at the full band workload:
+lmax = 10000, W_l = 0 above l = 1000, TT/EE/BB, 8 masks in one batched call,
+binned into 200 bins of 50 multipoles (the binning reading of the design doc R11),
+FP32C.  Checked against the oracle's band tier on seeded bins: rows of a bin
+are evaluated by the oracle and binned by the same rule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from _parity import TOL_FP32C, TOL_FP64, assert_parity
+
+pytestmark = pytest.mark.gpu
+
+LMAX, LCUT, WIDTH, NBIN = 10000, 1000, 50, 200
+SPEC3 = ("TT", "EE", "BB")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_gpu):
+    from paper_2602_15605_amd import couple
+    c = couple.couple_init(LMAX)
+    yield c
+    couple.couple_free(c)
+
+
+def _bin_rows(K_rows, b, edges):
+    """Binned row b from the oracle's rows l1 in bin b (all l2)."""
+    n = edges[b + 1] - edges[b]
+    out = np.zeros((K_rows.shape[0], len(edges) - 1))
+    for c in range(len(edges) - 1):
+        out[:, c] = K_rows[:, :, edges[c]:edges[c + 1]].sum(axis=(1, 2)) / n
+    return out
+
+
+def test_workload4_band_binned_8_masks(torch_gpu, ctx, oracle_bulk):
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    masks = [synth.workload_windows(4, mask=m) for m in range(8)]
+    dW = [[torch.as_tensor(masks[m][s]).cuda() for m in range(8)] for s in range(3)]
+    edges = np.arange(0, WIDTH * NBIN + 1, WIDTH)
+    Kb = couple.couple_band_batched(ctx, 0, LCUT, dW[0], None, dW[2], LMAX, spectra=SPEC3,
+                                    precision="fp32c", bin_edges=edges)
+    torch.cuda.synchronize()
+    Kb = Kb.cpu().numpy()
+    assert Kb.shape == (8, 3, NBIN, NBIN)
+    # bins further apart than the band are exactly 0
+    bb, bc = np.meshgrid(np.arange(NBIN), np.arange(NBIN), indexing="ij")
+    far = np.abs(bb - bc) * WIDTH - (WIDTH - 1) > LCUT
+    assert np.all(Kb[:, :, far] == 0.0)
+    rng = np.random.default_rng(4000)
+    for m in range(8):
+        bins = rng.choice(NBIN, 4 if m == 0 else 1, replace=False)
+        for b in bins:
+            rows = np.arange(edges[b], edges[b + 1])
+            Kr, Ar = oracle_bulk.coupling_rows(LMAX, masks[m][0], masks[m][1], masks[m][2], rows=rows,
+                                               spectra=SPEC3, l3_range=(0, LCUT), band_forward=True)
+            ref, refA = _bin_rows(Kr, b, edges), _bin_rows(Ar, b, edges)
+            for i, s in enumerate(SPEC3):
+                err = assert_parity(Kb[m, i, b], ref[i], refA[i], TOL_FP32C, "mask %d bin %d %s" % (m, b, s))
+                _say("mask %d bin %3d %s max rel err %.3e" % (m, b, s, err))
+    assert np.array_equal(Kb[:, 1], Kb[:, 2])
+
+
+def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk):
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    W = synth.workload_windows(4, mask=0)
+    dW = [torch.as_tensor(w).cuda() for w in W]
+    K = couple.couple_band(ctx, 0, LCUT, dW[0], dW[1], dW[2], LMAX, spectra=("TT", "TE", "EE"), precision="fp64")
+    rows = np.array([0, 1, 2, 3, 999, 1000, 1001, 4321, 9000, 9999, 10000])
+    got = K[:, torch.as_tensor(rows).cuda(), :].cpu().numpy()
+    del K
+    Kr, Ar = oracle_bulk.coupling_rows(LMAX, *W, rows=rows, spectra=("TT", "TE", "EE"), l3_range=(0, LCUT),
+                                       band_forward=True)
+    for i, s in enumerate(("TT", "TE", "EE")):
+        err = assert_parity(got[i], Kr[i], Ar[i], TOL_FP64, "band unbinned %s" % s)
+        _say("band unbinned fp64 %s max rel err %.3e" % (s, err))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32c", TOL_FP32C)])
+def test_band_batched_equals_single(torch_gpu, ctx, precision, tol):
+    """A batched call gives, mask by mask, what single calls give (bitwise)."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmax, lo, hi = 700, 3, 250
+    rng = np.random.default_rng(77)
+    Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(3)]
+    edges = [0, 2, 30, 100, 101, 400, 701]
+    Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws], [w[1] for w in Ws], [w[2] for w in Ws],
+                                    lmax, spectra=("TT", "TE", "EE", "BB"), precision=precision,
+                                    bin_edges=edges)
+    for m in range(3):
+        K1 = couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=("TT", "TE", "EE", "BB"), precision=precision,
+                                bin_edges=edges)
+        assert torch.equal(Kb[m], K1)

@@ -190,3 +190,34 @@ def test_linearity_symmetry_and_band(oracle_bulk):
     assert np.max(np.abs(Kb - Kz) / (Ab + 1e-300)) < 1e-15
     l1, l2 = np.meshgrid(np.arange(lmax + 1), np.arange(lmax + 1), indexing="ij")
     assert np.all(Kb[:, np.abs(l1 - l2) > hi] == 0.0)
+
+
+# ---- band-limited tier: forward recursion from the exact lower end ---------
+
+@pytest.mark.parametrize("l1,l2", [(3, 7), (10, 10), (2, 2), (50, 80), (300, 305), (999, 1999), (2, 600),
+                                   (4000, 4400), (6000, 5000)])
+@pytest.mark.parametrize("m", [0, -2])
+def test_forward_rows_equal_two_sided(oracle_bulk, l1, l2, m):
+    full = oracle_bulk.threej_row(l1, l2, m)
+    hi = min(l1 + l2, abs(l1 - l2) + 1200)
+    fw = oracle_bulk.threej_row_forward(l1, l2, m, hi)
+    ref = full[:len(fw)]
+    assert np.max(np.abs(fw - ref)) <= 2e-14 * np.max(np.abs(full))
+
+
+@pytest.mark.parametrize("l1,l2,l3,m", [(5000, 5600, 600, -2), (5000, 5600, 602, 0), (5000, 5600, 640, -2),
+                                        (9000, 8500, 500, -2), (9000, 8500, 520, 0)])
+def test_forward_rows_equal_sympy_large(oracle_bulk, l1, l2, l3, m):
+    fw = oracle_bulk.threej_row_forward(l1, l2, m, l3)
+    ref = float(wigner_3j(l1, l2, l3, m, -m, 0))
+    assert fw[-1] == pytest.approx(ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("lmax,lo,hi", [(400, 0, 100), (400, 17, 90), (300, 0, 600)])
+def test_band_rows_equal_restricted_full_rows(oracle_bulk, lmax, lo, hi):
+    Ws = [_rand_w(2 * lmax + 1, 50 + i) for i in range(3)]
+    rows = [0, 1, 2, 3, 57, 150, 299, lmax - 1, lmax]
+    Kf, Af = oracle_bulk.coupling_rows(lmax, *Ws, rows=rows, spectra=SPECS, l3_range=(lo, hi))
+    Kb, Ab = oracle_bulk.coupling_rows(lmax, *Ws, rows=rows, spectra=SPECS, l3_range=(lo, hi), band_forward=True)
+    assert np.max(np.abs(Kb - Kf) / (Af + 1e-300)) < 1e-13
+    assert np.array_equal(Kf == 0.0, Kb == 0.0)
