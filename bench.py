@@ -47,6 +47,58 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_extras(torch, couple, synth, args):
+    """The band-limited and batched workloads, timed the same way (device time
+    per call, inputs resident); reported beside the headline, not as it."""
+    out = {}
+    steps, warm = 3, 1
+    # band-limited: lmax=10000, l3<=1000, 8 masks, TT/EE/BB, 200 bins of 50, FP32C
+    L, cut = 10000, 1000
+    ctx = couple.couple_init(L)
+    masks = [synth.workload_windows(4, mask=m) for m in range(8)]
+    dW = [[torch.as_tensor(masks[m][s]).cuda() for m in range(8)] for s in range(3)]
+    edges = list(range(0, 10001, 50))
+    res = torch.empty((8, 3, 200, 200), dtype=torch.float64, device="cuda")
+    for prec in ("fp32c", "fp64"):
+        ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,
+                                                              spectra=("TT", "EE", "BB"), precision=prec,
+                                                              bin_edges=edges, out=res), steps, warm)
+        out["band_lmax10000_cut1000_8masks_binned_" + prec] = {
+            "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200}
+    couple.couple_free(ctx)
+    del dW, res
+    # batched: 32 masks, lmax uniform in [500, 4000], 4 spectra, matrix-core contraction
+    lmaxes = [int(x) for x in synth.batched_lmaxes()]
+    ctx = couple.couple_init(max(lmaxes))
+    Ws = [synth.workload_windows(3, mask=m) for m in range(len(lmaxes))]
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    outs = [torch.empty((4, L + 1, L + 1), dtype=torch.float64, device="cuda") for L in lmaxes]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    n_el = sum(4 * (L + 1) ** 2 for L in lmaxes)
+    for prec in ("mfma_fp32", "fp32c"):
+        ms = _timed(torch, lambda: couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=prec,
+                                                                outs=outs), steps, warm)
+        out["batched32_lmax500to4000_" + prec] = {"ms_per_call": ms, "k_elements_per_s": n_el / (ms * 1e-3),
+                                                   "masks": len(lmaxes), "elements": n_el}
+        print("[bench] batched %s: %.3f ms/call" % (prec, ms), file=sys.stderr, flush=True)
+    couple.couple_free(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +108,8 @@ def main():
     ap.add_argument("--lmax", type=int, default=6000)
     ap.add_argument("--cpu-rows", type=int, default=60, help="oracle rows timed for cpu_baseline (0: skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the band-limited and batched workload timings reported beside the headline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -160,6 +214,8 @@ def main():
                     assert np.all(K[i][~nz] == 0.0)
                 results[prec]["max_rel_err"] = errs
 
+    extras = {} if args.no_extras else run_extras(torch, couple, synth, args)
+
     head = "fp32c" if "ms_per_step" in results.get("fp32c", {}) else "fp64"
     h = results[head]
     strip_avg = h["kernel_ms"]["strip"]
@@ -186,6 +242,7 @@ def main():
                      "kernel": "strip (l3 reduction)", "flop_per_triple": FLOP_PER_TRIPLE_POL},
         "cpu_baseline": cpu,
         "precisions": results,
+        "other_workloads": extras,
     }
     print(json.dumps(line), flush=True)
     couple.couple_free(ctx)

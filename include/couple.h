@@ -56,8 +56,10 @@ enum couple_spectrum { COUPLE_TT = 1, COUPLE_TE = 2, COUPLE_EE = 4, COUPLE_BB = 
 /* arithmetic of the l3 reduction */
 enum couple_precision {
     COUPLE_FP64 = 0,   /* float64 throughout                                          */
-    COUPLE_FP32C = 1   /* float32 terms with compensated accumulation; float64 tables,
+    COUPLE_FP32C = 1,  /* float32 terms with compensated accumulation; float64 tables,
                           window scaling and final rescale                             */
+    COUPLE_MFMA_FP32 = 2 /* batched form only: float32 matrix-core contraction of the
+                            3j^2 tiles against the windows, Kahan-flushed accumulators */
 };
 
 /*
@@ -139,6 +141,39 @@ int couple_band_batched(couple_ctx *ctx, int n_masks, int l3_lo, int l3_hi, cons
                         const double *const *W_TP, const double *const *W_PP, int w_len, int lmax,
                         unsigned spectra, int precision, const int *bin_edges, int n_bins, double *out,
                         void *stream);
+
+/*
+ * couple_reserve_batched -- size the context's batched workspace for a batch
+ * of n_masks windows with the given lmax (HOST array).  Allocates (this is the
+ * one entry point besides couple_init that does); later batched calls of the
+ * same or smaller size allocate nothing.  Synchronises the device when the
+ * workspace grows.  Size: per group of 16 masks (sorted by lmax, L = the
+ * group's largest), 3 (L+1)(L+2)/2 x 16 float64 plus 3 (2L+1) x 16 float32.
+ * Errors: EINVAL (NULL ctx/lmax_i, n_masks outside [1, 64], lmax > lmax_max),
+ * ENOMEM.
+ */
+int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
+
+/*
+ * couple_matrix_batched -- full coupling matrices for n_masks windows of
+ * uneven lmax in one call (Sec. 2 eqs. K_TT, K_EE; App. A, per mask).
+ *   lmax_i, w_len_i : HOST arrays of n_masks ints (w_len_i[m] >= 2 lmax_i[m] + 1).
+ *   W_TT, W_TP, W_PP: HOST arrays of n_masks DEVICE float64 pointers (an
+ *                     array may be NULL when no requested spectrum uses it).
+ *   out             : HOST array of n_masks DEVICE float64 pointers; mask m
+ *                     gets popcount(spectra) (lmax_i[m]+1)^2 entries in the
+ *                     couple_matrix layout.
+ *   precision       : COUPLE_MFMA_FP32 -- one launch for the whole batch: masks
+ *                     sorted by lmax in groups of 16 sharing every generated
+ *                     3j^2 tile on the matrix cores; needs
+ *                     couple_reserve_batched first.
+ *                     COUPLE_FP64 / COUPLE_FP32C -- couple_matrix per mask.
+ * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),
+ * EDEVICE.
+ */
+int couple_matrix_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const double *const *W_TT,
+                          const double *const *W_TP, const double *const *W_PP, const int *w_len_i,
+                          unsigned spectra, int precision, double *const *out, void *stream);
 
 /*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for

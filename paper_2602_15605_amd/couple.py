@@ -21,7 +21,7 @@ COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EDEVICE, COUPLE_ENOTSUP = 0, -1,
 TT, TE, EE, BB = 1, 2, 4, 8
 SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB}
 SPECTRUM_ORDER = ("TT", "TE", "EE", "BB")
-PRECISIONS = {"fp64": 0, "fp32c": 1}
+PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2}
 LMAX_LIMIT = 16384
 
 
@@ -57,6 +57,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_band.restype = i
     lib.couple_band_batched.argtypes = [vp, i, i, i, vp, vp, vp, i, i, u, i, vp, i, dp, vp]
     lib.couple_band_batched.restype = i
+    lib.couple_reserve_batched.argtypes = [vp, i, vp]
+    lib.couple_reserve_batched.restype = i
+    lib.couple_matrix_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, u, i, vp, vp]
+    lib.couple_matrix_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
     lib.couple_profile.argtypes = [vp, i]
@@ -227,6 +231,40 @@ def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT"
         edges.ctypes.data if edges is not None else None, n_bins, _dev_ptr(out, "out"), _stream_handle(stream))
     _check(rc, ctx)
     return out
+
+
+def couple_reserve_batched(ctx, lmax_list) -> None:
+    """Size the context's batched workspace for masks of these lmax."""
+    lm = np.ascontiguousarray(np.asarray(lmax_list, dtype=np.int32))
+    _check(load_library().couple_reserve_batched(ctx.handle, len(lm), lm.ctypes.data), ctx)
+
+
+def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE", "EE", "BB"),
+                          precision="mfma_fp32", outs=None, stream=None):
+    """Coupling matrices for a list of masks of uneven lmax in one call.
+
+    ``W_*`` are lists of float64 GPU tensors (or None); returns a list of
+    [n_spec, lmax_m+1, lmax_m+1] tensors.
+    """
+    import torch
+    bits = _spectra_bits(spectra)
+    ns = max(_n_spec(bits), 1)
+    lm = np.ascontiguousarray(np.asarray(lmax_list, dtype=np.int32))
+    n = len(lm)
+    lists = [W_TT, W_TP, W_PP]
+    dev = next(w[0].device for w in lists if w is not None)
+    if outs is None:
+        outs = [torch.empty((ns, int(L) + 1, int(L) + 1), dtype=torch.float64, device=dev) for L in lm]
+    wl = np.ascontiguousarray(np.array([min(int(w[m].numel()) for w in lists if w is not None) for m in range(n)],
+                                       dtype=np.int32))
+    arrs = [_ptr_array(w, nm)[0] for w, nm in zip(lists, ("W_TT", "W_TP", "W_PP"))]
+    optr = (ctypes.c_void_p * n)(*[_dev_ptr(o, "out") for o in outs])
+    prec = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
+    rc = load_library().couple_matrix_batched(
+        ctx.handle, n, lm.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs],
+        wl.ctypes.data, bits, prec, ctypes.cast(optr, ctypes.c_void_p), _stream_handle(stream))
+    _check(rc, ctx)
+    return outs
 
 
 def couple_tables(ctx):

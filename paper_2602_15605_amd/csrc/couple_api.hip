@@ -76,6 +76,8 @@ struct Timed {
 void release(couple_ctx* c) {
     if (!c) return;
     (void)drain_marks(c);
+    if (c->pending_start) (void)hipEventDestroy(c->pending_start);
+    (void)hipFree(c->bws);
     (void)hipFree(c->g_pad);
     (void)hipFree(c->h_pad);
     (void)hipFree(c->gf_pad);
@@ -141,6 +143,31 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
 }
 
 }  // namespace
+
+namespace couple {
+
+void prof_begin(couple_ctx* c, hipStream_t s) {
+    if (!c->profiling) return;
+    if (c->pending_start) (void)hipEventDestroy(c->pending_start);
+    c->pending_start = nullptr;
+    hipEvent_t a = nullptr;
+    if (hipEventCreate(&a) == hipSuccess && hipEventRecord(a, s) == hipSuccess) c->pending_start = a;
+    else if (a) (void)hipEventDestroy(a);
+}
+
+void prof_end(couple_ctx* c, hipStream_t s, int stage) {
+    if (!c->profiling || !c->pending_start) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
+        c->marks.push_back({c->pending_start, b, stage});
+    } else {
+        (void)hipEventDestroy(c->pending_start);
+        if (b) (void)hipEventDestroy(b);
+    }
+    c->pending_start = nullptr;
+}
+
+}  // namespace couple
 
 extern "C" {
 
@@ -342,6 +369,132 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
                       out + m * per_mask, s);
         if (rc) return rc;
     }
+    return COUPLE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Sort masks by lmax (descending, stable) into column groups of 16.
+int make_plan(couple_ctx* ctx, int n_masks, const int* lmax_i, couple::BatchPlan* p, int* order) {
+    if (n_masks < 1 || n_masks > couple::kMaxGroups * couple::kMaskGroup)
+        return fail(ctx, COUPLE_EINVAL, "n_masks=%d outside [1, %d]", n_masks,
+                    couple::kMaxGroups * couple::kMaskGroup);
+    if (!lmax_i) return fail(ctx, COUPLE_EINVAL, "lmax_i is NULL");
+    for (int m = 0; m < n_masks; ++m) {
+        if (lmax_i[m] < 0 || lmax_i[m] > ctx->lmax_max)
+            return fail(ctx, COUPLE_EINVAL, "mask %d: lmax=%d outside [0, lmax_max=%d]", m, lmax_i[m],
+                        ctx->lmax_max);
+        order[m] = m;
+    }
+    for (int i = 1; i < n_masks; ++i) {
+        const int v = order[i];
+        int j = i;
+        while (j > 0 && lmax_i[order[j - 1]] < lmax_i[v]) {
+            order[j] = order[j - 1];
+            --j;
+        }
+        order[j] = v;
+    }
+    p->n_groups = (n_masks + couple::kMaskGroup - 1) / couple::kMaskGroup;
+    for (int gi = 0; gi < p->n_groups; ++gi) {
+        p->n_masks[gi] = std::min(couple::kMaskGroup, n_masks - gi * couple::kMaskGroup);
+        p->L[gi] = lmax_i[order[gi * couple::kMaskGroup]];
+        for (int m = 0; m < couple::kMaskGroup; ++m) {
+            p->lmax[gi][m] = m < p->n_masks[gi] ? lmax_i[order[gi * couple::kMaskGroup + m]] : -1;
+            p->out[gi][m] = nullptr;
+            for (int x = 0; x < 3; ++x) p->w[gi][x][m] = nullptr;
+        }
+    }
+    return COUPLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int couple_reserve_batched(couple_ctx* ctx, int n_masks, const int* lmax_i) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    couple::BatchPlan p;
+    int order[couple::kMaxGroups * couple::kMaskGroup];
+    int rc = make_plan(ctx, n_masks, lmax_i, &p, order);
+    if (rc) return rc;
+    const size_t need = couple::batched_workspace_bytes(p);
+    if (need <= ctx->bws_bytes) return COUPLE_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "sync before workspace change");
+    (void)hipFree(ctx->bws);
+    ctx->bws = nullptr;
+    ctx->bws_bytes = 0;
+    e = hipMalloc(&ctx->bws, need);
+    if (e != hipSuccess) {
+        ctx->bws = nullptr;
+        return fail(ctx, COUPLE_ENOMEM, "hipMalloc of %zu bytes for the batched workspace: %s", need,
+                    hipGetErrorString(e));
+    }
+    ctx->bws_bytes = need;
+    return COUPLE_OK;
+}
+
+int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const double* const* W_TT,
+                          const double* const* W_TP, const double* const* W_PP, const int* w_len_i,
+                          unsigned spectra, int precision, double* const* out, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    couple::BatchPlan p;
+    int order[couple::kMaxGroups * couple::kMaskGroup];
+    int rc = make_plan(ctx, n_masks, lmax_i, &p, order);
+    if (rc) return rc;
+    if (!w_len_i || !out) return fail(ctx, COUPLE_EINVAL, "w_len_i or out is NULL");
+    const bool need_tt = spectra & COUPLE_TT, need_tp = spectra & COUPLE_TE,
+               need_pp = spectra & (COUPLE_EE | COUPLE_BB);
+    if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
+        return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
+    const bool mfma = precision == COUPLE_MFMA_FP32;
+    for (int m = 0; m < n_masks; ++m) {
+        rc = check_common(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
+                          need_pp ? W_PP[m] : nullptr, lmax_i[m], spectra, mfma ? COUPLE_FP64 : precision,
+                          out[m]);
+        if (rc == COUPLE_OK && w_len_i[m] < 2 * lmax_i[m] + 1)
+            rc = fail(ctx, COUPLE_EINVAL, "w_len=%d < 2*lmax+1=%d", w_len_i[m], 2 * lmax_i[m] + 1);
+        if (rc) {
+            ctx->err = "mask " + std::to_string(m) + ": " + ctx->err;
+            return rc;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!mfma) {
+        // float64 / float32-compensated: one couple_matrix per mask, back to back on s
+        for (int m = 0; m < n_masks; ++m) {
+            rc = couple_matrix(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
+                               need_pp ? W_PP[m] : nullptr, w_len_i[m], lmax_i[m], spectra, precision, out[m],
+                               stream);
+            if (rc) {
+                ctx->err = "mask " + std::to_string(m) + ": " + ctx->err;
+                return rc;
+            }
+        }
+        return COUPLE_OK;
+    }
+    const size_t need = couple::batched_workspace_bytes(p);
+    if (need > ctx->bws_bytes)
+        return fail(ctx, COUPLE_EINVAL, "batched workspace too small (%zu < %zu bytes): call couple_reserve_batched",
+                    ctx->bws_bytes, need);
+    for (int gi = 0; gi < p.n_groups; ++gi)
+        for (int m = 0; m < p.n_masks[gi]; ++m) {
+            const int src = order[gi * couple::kMaskGroup + m];
+            p.w[gi][0][m] = need_tt ? W_TT[src] : nullptr;
+            p.w[gi][1][m] = need_tp ? W_TP[src] : nullptr;
+            p.w[gi][2][m] = need_pp ? W_PP[src] : nullptr;
+            p.out[gi][m] = out[src];
+        }
+    p.flush = ctx->batched_flush;
+    int src4[4];
+    const int n_out = output_sources(spectra, src4);
+    hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
     return COUPLE_OK;
 }
 

@@ -35,6 +35,19 @@ __host__ __device__ inline long long tri_size(int lmax) {
     return (long long)(lmax + 1) * (lmax + 2) / 2;
 }
 
+// Batched form: masks sorted by lmax and split into column groups of 16.
+constexpr int kMaxGroups = 4;          // up to 64 masks per call
+constexpr int kMaskGroup = 16;
+struct BatchPlan {
+    int n_groups = 0;
+    int n_masks[kMaxGroups] = {0, 0, 0, 0};
+    int L[kMaxGroups] = {0, 0, 0, 0};              // largest lmax of the group
+    int lmax[kMaxGroups][kMaskGroup];
+    const double* w[kMaxGroups][3][kMaskGroup];    // W_TT, W_TP, W_PP (NULL: unused)
+    double* out[kMaxGroups][kMaskGroup];
+    int flush = 8;                                  // MFMA steps per Kahan flush
+};
+
 }  // namespace couple
 
 struct couple_ctx {
@@ -52,6 +65,9 @@ struct couple_ctx {
     float* wpf = nullptr;        // float32 copies
     int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
     int* edges_host = nullptr;   // pinned staging for the bin edges
+    void* bws = nullptr;         // batched workspace (couple_reserve_batched)
+    size_t bws_bytes = 0;
+    int batched_flush = 8;       // MFMA steps per Kahan flush of the batched kernel
     std::string err;
     // measurement hook: event pairs recorded around each kernel
     bool profiling = false;
@@ -60,6 +76,7 @@ struct couple_ctx {
         int stage;
     };
     std::vector<Mark> marks;
+    hipEvent_t pending_start = nullptr;
     double prof_ms[COUPLE_N_STAGES] = {0, 0, 0};
     int prof_count[COUPLE_N_STAGES] = {0, 0, 0};
 };
@@ -84,5 +101,14 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
                       const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
 // out[0 .. n) = 0 with a kernel (safe inside captured graphs)
 hipError_t launch_zero(double* out, size_t n, hipStream_t s);
+
+// measurement hook: event marks around a kernel of stage `stage` (no-op unless profiling)
+void prof_begin(couple_ctx* ctx, hipStream_t s);
+void prof_end(couple_ctx* ctx, hipStream_t s, int stage);
+
+// batched form (batched.hip)
+size_t batched_workspace_bytes(const BatchPlan& p);
+hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, const int* spec_src, int n_out,
+                          hipStream_t s);
 
 }  // namespace couple

@@ -1,0 +1,115 @@
+"""Batched form: many masks of uneven lmax in one call, contracted on the
+matrix cores (COUPLE_MFMA_FP32), checked per mask against the oracle.
+
+The workload is 32 synthetic masks with lmax uniform in [500, 4000]; every
+mask is compared on >= 1% of its rows (at least 5, plus rows 0, 1, 2, lmax).
+Small full-matrix cases cover the group edges: masks of very different lmax
+sharing a 16-mask column group, a second group with one mask, lmax 0..3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from _parity import TOL_FP32C, assert_parity
+
+pytestmark = pytest.mark.gpu
+
+SPEC4 = ("TT", "TE", "EE", "BB")
+TOL_MFMA = TOL_FP32C
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_gpu):
+    from paper_2602_15605_amd import couple
+    c = couple.couple_init(4000)
+    yield c
+    couple.couple_free(c)
+
+
+def _rand_windows(lmaxes, seed):
+    rng = np.random.default_rng(seed)
+    return [[rng.uniform(0.05, 1.5, 2 * L + 1) for _ in range(3)] for L in lmaxes]
+
+
+def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk):
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [257, 3, 64, 0, 65, 200, 1, 130, 17, 2, 255, 100, 31, 32, 33, 150, 90]   # 17 masks: 2 groups
+    Ws = _rand_windows(lmaxes, 5)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision="mfma_fp32")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, L in enumerate(lmaxes):
+        K = outs[m].cpu().numpy()
+        Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], spectra=SPEC4)
+        for i, s in enumerate(SPEC4):
+            worst = max(worst, assert_parity(K[i], Kr[i], Ar[i], TOL_MFMA, "mask %d lmax %d %s" % (m, L, s)))
+        assert np.array_equal(K[2], K[3])
+    _say("batched small: max rel err %.3e" % worst)
+
+
+def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk):
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    lmaxes = [int(x) for x in synth.batched_lmaxes()]
+    Ws = [synth.workload_windows(3, mask=m) for m in range(len(lmaxes))]
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision="mfma_fp32")
+    torch.cuda.synchronize()
+    worst = {s: 0.0 for s in SPEC4}
+    for m, L in enumerate(lmaxes):
+        rows = synth.sample_rows(L, fraction=0.01, seed=3000 + m, minimum=5)
+        got = outs[m][:, torch.as_tensor(rows.astype(np.int64)).cuda(), :].cpu().numpy()
+        Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], rows=rows, spectra=SPEC4)
+        for i, s in enumerate(SPEC4):
+            worst[s] = max(worst[s], assert_parity(got[i], Kr[i], Ar[i], TOL_MFMA, "mask %d lmax %d %s" % (m, L, s)))
+    _say("workload3 batched mfma_fp32 max rel err: " + ", ".join("%s %.3e" % kv for kv in worst.items()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision):
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [40, 300, 7]
+    Ws = _rand_windows(lmaxes, 8)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
+    for m in range(3):
+        K1 = couple.couple_matrix(ctx, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=SPEC4, precision=precision)
+        assert torch.equal(outs[m], K1)
+
+
+def test_batched_errors(torch_gpu, ctx):
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    w = [torch.ones(81, dtype=torch.float64, device="cuda")]
+    with pytest.raises(couple.CoupleError, match="lmax"):
+        couple.couple_matrix_batched(ctx, [4001], [torch.ones(8003, dtype=torch.float64, device="cuda")],
+                                     None, None, spectra=("TT",))
+    with pytest.raises(couple.CoupleError, match="w_len"):
+        couple.couple_matrix_batched(ctx, [41], w, None, None, spectra=("TT",))
+    with pytest.raises(couple.CoupleError, match="n_masks"):
+        couple.couple_reserve_batched(ctx, list(range(65)))
+    fresh = couple.couple_init(100)
+    try:
+        with pytest.raises(couple.CoupleError, match="couple_reserve_batched"):
+            couple.couple_matrix_batched(fresh, [40], w, None, None, spectra=("TT",), precision="mfma_fp32")
+    finally:
+        couple.couple_free(fresh)
