@@ -176,6 +176,26 @@ int couple_matrix_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const
                           unsigned spectra, int precision, double *const *out, void *stream);
 
 /*
+ * Tile shape of the batched matrix-core kernel (COUPLE_MFMA_FP32):
+ * row_tiles 16-row tiles of one diagonal per wavefront (1, 2 or 4) and the
+ * number of 4-k MFMA steps between Kahan flushes of the float32 matrix-core
+ * accumulators (1..16; fewer flushes are faster, more accurate the fewer
+ * steps).  Defaults: 2 and 8.
+ *
+ * couple_autotune_batched times every (row_tiles in {1,2,4}, flush in {4,8})
+ * on the given batch (same arguments as couple_matrix_batched; out is
+ * overwritten), keeps the fastest in ctx for later batched calls and returns
+ * it through the optional HOST pointers.  Synchronises the stream.
+ * Errors: as couple_matrix_batched; EINVAL for a bad tile shape.
+ */
+int couple_set_batched_tiles(couple_ctx *ctx, int row_tiles, int flush);
+int couple_get_batched_tiles(const couple_ctx *ctx, int *row_tiles, int *flush);
+int couple_autotune_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const double *const *W_TT,
+                            const double *const *W_TP, const double *const *W_PP, const int *w_len_i,
+                            unsigned spectra, double *const *out, void *stream, int *best_row_tiles,
+                            int *best_flush, float *best_ms);
+
+/*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for
  * inspection and tests).  Any pointer may be NULL to skip that table.
  *   g    : lmax_max + 1 float64,   g[p] = g(p)                  (eq. gdef)

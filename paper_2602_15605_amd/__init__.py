@@ -6,5 +6,6 @@ seeded synthetic window spectra.
 """
 from .couple import (BB, EE, TE, TT, CoupleError, Context, couple_band, couple_band_batched, couple_free,  # noqa: F401
                      couple_init, couple_last_error, couple_matrix, couple_matrix_batched, couple_profile,
-                     couple_profile_read, couple_reserve_batched,
+                     couple_profile_read, couple_reserve_batched, couple_autotune_batched,
+                     couple_set_batched_tiles, couple_get_batched_tiles,
                      couple_tables, load_library)

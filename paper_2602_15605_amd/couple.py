@@ -61,6 +61,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_reserve_batched.restype = i
     lib.couple_matrix_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, u, i, vp, vp]
     lib.couple_matrix_batched.restype = i
+    lib.couple_set_batched_tiles.argtypes = [vp, i, i]
+    lib.couple_set_batched_tiles.restype = i
+    lib.couple_get_batched_tiles.argtypes = [vp, vp, vp]
+    lib.couple_get_batched_tiles.restype = i
+    lib.couple_autotune_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, u, vp, vp, vp, vp, vp]
+    lib.couple_autotune_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
     lib.couple_profile.argtypes = [vp, i]
@@ -265,6 +271,42 @@ def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE",
         wl.ctypes.data, bits, prec, ctypes.cast(optr, ctypes.c_void_p), _stream_handle(stream))
     _check(rc, ctx)
     return outs
+
+
+def couple_set_batched_tiles(ctx, row_tiles: int, flush: int) -> None:
+    _check(load_library().couple_set_batched_tiles(ctx.handle, int(row_tiles), int(flush)), ctx)
+
+
+def couple_get_batched_tiles(ctx):
+    tm, fl = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().couple_get_batched_tiles(ctx.handle, ctypes.byref(tm), ctypes.byref(fl)), ctx)
+    return tm.value, fl.value
+
+
+def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE", "EE", "BB"), outs=None,
+                            stream=None):
+    """Time the batched kernel's tile shapes on this batch; keep and return the best
+    as (row_tiles, flush, ms)."""
+    import torch
+    bits = _spectra_bits(spectra)
+    ns = max(_n_spec(bits), 1)
+    lm = np.ascontiguousarray(np.asarray(lmax_list, dtype=np.int32))
+    n = len(lm)
+    lists = [W_TT, W_TP, W_PP]
+    dev = next(w[0].device for w in lists if w is not None)
+    if outs is None:
+        outs = [torch.empty((ns, int(L) + 1, int(L) + 1), dtype=torch.float64, device=dev) for L in lm]
+    wl = np.ascontiguousarray(np.array([min(int(w[m].numel()) for w in lists if w is not None) for m in range(n)],
+                                       dtype=np.int32))
+    arrs = [_ptr_array(w, nm)[0] for w, nm in zip(lists, ("W_TT", "W_TP", "W_PP"))]
+    optr = (ctypes.c_void_p * n)(*[_dev_ptr(o, "out") for o in outs])
+    tm, fl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    rc = load_library().couple_autotune_batched(
+        ctx.handle, n, lm.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs],
+        wl.ctypes.data, bits, ctypes.cast(optr, ctypes.c_void_p), _stream_handle(stream), ctypes.byref(tm),
+        ctypes.byref(fl), ctypes.byref(ms))
+    _check(rc, ctx)
+    return tm.value, fl.value, ms.value
 
 
 def couple_tables(ctx):

@@ -16,7 +16,8 @@
 //     step of 4 k it generates its A elements on the VALU (one per lane and
 //     row tile, the v_mfma_f32_16x16x4f32 operand layout: lane l holds row
 //     l % 16, k offset l / 16) and issues 3*TM MFMAs against the W' tile
-//     (k x 16 masks, lane l holds k offset l / 16, mask l % 16) staged in LDS;
+//     (k x 16 masks, lane l holds k offset l / 16, mask l % 16), loaded from
+//     the L2-resident W' table two steps ahead of its use;
 //   * every kFlush MFMA steps the float32 matrix-core accumulators are added
 //     into Kahan (sum, compensation) pairs, which bounds the float32
 //     accumulation error to a few ulp per block;
@@ -25,6 +26,8 @@
 //     writes in 128-byte rows.
 // A fill pass then writes each mask's K (mask-major; columns beyond a mask's
 // own lmax are not written).
+#include <type_traits>
+
 #include "couple_internal.hpp"
 
 namespace couple {
@@ -77,8 +80,7 @@ batched_mfma_f32_kernel(BatchArgs a) {
     __shared__ float s_g[W::kLen];
     __shared__ float s_h[W::kLen];
     __shared__ float s_s[KC + 4];       // S(k) = g(k) g(d+k), float32
-    __shared__ int s_c[KC + 4];         // c(k) = l3 (l3 + 1)
-    __shared__ float s_w[3][KC + 4][kGroup];
+    __shared__ float s_dc[KC + 4];      // D(k) = c(k) - c(chunk start), exact in float32
 
     // ---- work item: group, then level b (descending), diagonal d ----
     int item = blockIdx.x;
@@ -103,10 +105,11 @@ batched_mfma_f32_kernel(BatchArgs a) {
 
     const int lane = threadIdx.x;
     const int r = lane & 15, q = lane >> 4;
-    const float* wt = a.wtab + a.wt_off[grp];
     const int wl = 2 * L + 1;
+    // B operand: W'_X(l3)[mask r] with l3 = d + 2k, k = 4 step + q
+    const float* wt = a.wtab + a.wt_off[grp] + r;
+    const long long xs = (long long)wl * kGroup;    // stride between spectra
 
-    // per row tile: l1 of this lane's A element, gamma = a + b - 1, beta = 2ab + 1
     int gam[TM];
     float beta[TM];
 #pragma unroll
@@ -127,11 +130,24 @@ batched_mfma_f32_kernel(BatchArgs a) {
             for (int i = 0; i < 4; ++i) ks[t][x][i] = kc[t][x][i] = 0.0f;
         }
 
+    const int n_steps = (kmax + 4) / 4;          // steps of 4 k
+    // B prefetch two steps ahead (0 beyond the row or the window)
+    auto load_b = [&](int step, float* bv) {
+        const int l3 = d + 2 * (4 * step + q);
+        const bool ok = step < n_steps && l3 < wl;
+        const float* p = wt + (long long)l3 * kGroup;
+        bv[0] = ok ? p[0] : 0.0f;
+        bv[1] = ok ? p[xs] : 0.0f;
+        bv[2] = ok ? p[2 * xs] : 0.0f;
+    };
+    float b0[3], b1[3];
+    load_b(0, b0);
+    load_b(1, b1);
+
     int since_flush = 0;
     for (int k0 = 0; k0 <= kmax; k0 += KC) {
         const int kc_n = min(KC, kmax - k0 + 1);
         __syncthreads();
-        // g(l1 - k): slot = l1 - k - (A0 - k0 - KC - 3); h(l1 + d + k): slot = l1 + d + k - (A0 + d + k0)
         const int g_base = A0 - k0 - KC - 3;
         const int h_base = A0 + d + k0;
         for (int slot = lane; slot < W::kLen; slot += kBThreads) {
@@ -139,44 +155,44 @@ batched_mfma_f32_kernel(BatchArgs a) {
             s_g[slot] = (eg >= 0 && eg < a.g_len) ? a.gf[eg] : 0.0f;
             s_h[slot] = (eh >= 0 && eh < a.h_len) ? a.hf[eh] : 0.0f;
         }
+        const int l3c = d + 2 * k0;
         for (int s = lane; s < KC + 4; s += kBThreads) {
-            float sv = 0.0f;
-            int cv = 0;
+            float sv = 0.0f, dv = 0.0f;
             if (s < kc_n) {
                 const int k = k0 + s;
                 sv = (float)(a.g[k] * a.g[d + k]);
                 const int l3 = d + 2 * k;
-                cv = l3 * (l3 + 1);
+                dv = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
             }
             s_s[s] = sv;
-            s_c[s] = cv;
+            s_dc[s] = dv;
         }
-        {
-            // W' rows l3 = d + 2k of the chunk, 16 masks each: lane = (row offset, mask)
-            const int m = lane & (kGroup - 1);
-            for (int s = lane >> 4; s < KC + 4; s += kBThreads / kGroup) {
-                const int l3 = d + 2 * (k0 + s);
-                const bool ok = s < kc_n && l3 < wl;
+        // t = T + D(k), T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly
+        float thi[TM], tlo[TM];
 #pragma unroll
-                for (int x = 0; x < 3; ++x)
-                    s_w[x][s][m] = ok ? wt[((long long)x * wl + l3) * kGroup + m] : 0.0f;
-            }
+        for (int t = 0; t < TM; ++t) {
+            const int T = l3c * (l3c + 1) - gam[t];
+            thi[t] = (float)T;
+            tlo[t] = (float)(T - (int)thi[t]);
         }
         __syncthreads();
 
         for (int s0 = 0; s0 < kc_n; s0 += 4) {
             const int s = s0 + q;                 // this lane's k offset in the chunk
             const float S = s_s[s];
-            const int c = s_c[s];
-            const float btt = s_w[0][s][r], btp = s_w[1][s][r], bpp = s_w[2][s][r];
+            const float D = s_dc[s];
+            const float btt = b0[0], btp = b0[1], bpp = b0[2];
+            b0[0] = b1[0];
+            b0[1] = b1[1];
+            b0[2] = b1[2];
+            load_b((k0 + s0) / 4 + 2, b1);
 #pragma unroll
             for (int t = 0; t < TM; ++t) {
                 const int l1 = A0 + 16 * t + r;
-                // k = k0 + s: g slot l1 - k - g_base, h slot l1 + d + k - h_base
                 const float gv = s_g[l1 - (k0 + s) - g_base];
                 const float hv = s_h[l1 - A0 + s];
                 const float x2 = S * (gv * hv);
-                const float tt = (float)(c - gam[t]);
+                const float tt = thi[t] + (D + tlo[t]);
                 const float N = __builtin_fmaf(tt, tt, -beta[t]);
                 const float y = x2 * N;
                 const float z = y * N;
@@ -386,8 +402,8 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
         if (e != hipSuccess) return e;
     }
     // contraction
-    {
-        constexpr int TM = 2;
+    auto contract = [&](auto tm_tag) -> hipError_t {
+        constexpr int TM = decltype(tm_tag)::value;
         BatchArgs a;
         a.n_groups = p.n_groups;
         long long total = 0;
@@ -418,7 +434,16 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
         prof_begin(ctx, s);
         hipLaunchKernelGGL(batched_mfma_f32_kernel<TM>, dim3((unsigned)total), dim3(kBThreads), 0, s, a);
         prof_end(ctx, s, 1);
-        hipError_t e = hipGetLastError();
+        return hipGetLastError();
+    };
+    {
+        hipError_t e;
+        if (p.tm == 1)
+            e = contract(std::integral_constant<int, 1>());
+        else if (p.tm == 4)
+            e = contract(std::integral_constant<int, 4>());
+        else
+            e = contract(std::integral_constant<int, 2>());
         if (e != hipSuccess) return e;
     }
     // fill

@@ -491,10 +491,84 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
             p.out[gi][m] = out[src];
         }
     p.flush = ctx->batched_flush;
+    p.tm = ctx->batched_tm;
     int src4[4];
     const int n_out = output_sources(spectra, src4);
     hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
+    return COUPLE_OK;
+}
+
+int couple_set_batched_tiles(couple_ctx* ctx, int row_tiles, int flush) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (row_tiles != 1 && row_tiles != 2 && row_tiles != 4)
+        return fail(ctx, COUPLE_EINVAL, "row_tiles=%d: must be 1, 2 or 4", row_tiles);
+    if (flush < 1 || flush > 16) return fail(ctx, COUPLE_EINVAL, "flush=%d outside [1, 16]", flush);
+    ctx->batched_tm = row_tiles;
+    ctx->batched_flush = flush;
+    return COUPLE_OK;
+}
+
+int couple_get_batched_tiles(const couple_ctx* ctx, int* row_tiles, int* flush) {
+    if (!ctx) return COUPLE_EINVAL;
+    if (row_tiles) *row_tiles = ctx->batched_tm;
+    if (flush) *flush = ctx->batched_flush;
+    return COUPLE_OK;
+}
+
+int couple_autotune_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const double* const* W_TT,
+                            const double* const* W_TP, const double* const* W_PP, const int* w_len_i,
+                            unsigned spectra, double* const* out, void* stream, int* best_row_tiles,
+                            int* best_flush, float* best_ms) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    static const int kTm[] = {1, 2, 4};
+    static const int kFlush[] = {4, 8};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, COUPLE_EDEVICE, "event creation failed");
+    const int tm0 = ctx->batched_tm, fl0 = ctx->batched_flush;
+    float best = 3.4e38f;
+    int btm = tm0, bfl = fl0, rc = COUPLE_OK;
+    for (int tm : kTm)
+        for (int fl : kFlush) {
+            ctx->batched_tm = tm;
+            ctx->batched_flush = fl;
+            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, COUPLE_MFMA_FP32,
+                                       out, stream);  // warm-up (and argument check)
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, COUPLE_MFMA_FP32,
+                                       out, stream);
+            (void)hipEventRecord(e1, s);
+            if (rc) break;
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(ctx, e, "autotune timing");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                btm = tm;
+                bfl = fl;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        ctx->batched_tm = tm0;
+        ctx->batched_flush = fl0;
+        return rc;
+    }
+    ctx->batched_tm = btm;
+    ctx->batched_flush = bfl;
+    if (best_row_tiles) *best_row_tiles = btm;
+    if (best_flush) *best_flush = bfl;
+    if (best_ms) *best_ms = best;
     return COUPLE_OK;
 }
 

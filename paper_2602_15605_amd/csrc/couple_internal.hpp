@@ -46,6 +46,7 @@ struct BatchPlan {
     const double* w[kMaxGroups][3][kMaskGroup];    // W_TT, W_TP, W_PP (NULL: unused)
     double* out[kMaxGroups][kMaskGroup];
     int flush = 8;                                  // MFMA steps per Kahan flush
+    int tm = 2;                                     // 16-row tiles per wavefront (1, 2, 4)
 };
 
 }  // namespace couple
@@ -68,6 +69,7 @@ struct couple_ctx {
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
     int batched_flush = 8;       // MFMA steps per Kahan flush of the batched kernel
+    int batched_tm = 2;          // row tiles per wavefront of the batched kernel
     std::string err;
     // measurement hook: event pairs recorded around each kernel
     bool profiling = false;

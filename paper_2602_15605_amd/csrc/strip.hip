@@ -177,10 +177,11 @@ strip_fp64_kernel(StripArgs a) {
         }
         // steps are taken in groups of R; the staged U of steps past kc is 0
         const int kc_r = (kc + R - 1) / R * R;
-        for (int s0 = 0; s0 < kc_r; s0 += R) {
-            // phys(R lane + KC - 1 - s) and phys(R lane + R - 1 + s) for s = s0 + u
-            const double* pg = s_g + (R + 1) * (lane + (KC - s0) / R - 1) + (R - 1);
-            const double* ph = s_h + (R + 1) * (lane + s0 / R) + (R - 1);
+        // phys(R lane + KC - 1 - s) and phys(R lane + R - 1 + s) for s = s0 + u:
+        // per group of R steps the g pointer moves down and the h pointer up by R + 1
+        const double* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
+        const double* ph = s_h + (R + 1) * lane + (R - 1);
+        for (int s0 = 0; s0 < kc_r; s0 += R, pg -= R + 1, ph += R + 1) {
             const double4* pu = s_u + s0;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -231,9 +232,14 @@ strip_fp64_kernel(StripArgs a) {
 //       double-double build),
 //   U_X(k) formed in float64 from the float64 tables and windows and rounded
 //       once to float32,
-//   N' = t^2 - (2ab + 1) with t = c - (a + b - 1) taken exactly in int32 and
-//       rounded once to float32 (the subtraction cancels, so it must not be
-//       done in float32), then one fused multiply-add.
+//   N' = t^2 - (2ab + 1) with t = c - (a + b - 1).  The subtraction cancels
+//       (t is small when l1 << l2), so t is formed from exact pieces: per lane
+//       and chunk the integer T = c(chunk start) - (a + b - 1) is split into
+//       float32 T_hi + T_lo exactly, the staged per-step value is the integer
+//       D(k) = c(k) - c(chunk start) (|D| < 2^24, exact in float32), and
+//       t = T_hi + (D + T_lo) is rounded once -- two float32 adds instead of an
+//       integer subtraction and a half-rate int-to-float conversion.  Then
+//       one fused multiply-add gives N'.
 // Accumulation: each lane sums kCompBlock consecutive terms with float32 FMA
 // and adds the block sum into a Kahan (sum, compensation) pair in float32;
 // the pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.
@@ -305,9 +311,10 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                 const double gg = a.g[k] * a.g[d + k];
                 u.x = (float)(wtt[l3] * gg);
                 if (POL) {
+                    const int l3c = d + 2 * k0;
                     u.y = (float)(wtp[l3] * gg);
                     u.z = (float)(wpp[l3] * gg);
-                    u.w = __int_as_float(l3 * (l3 + 1));
+                    u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
                 }
             }
             s_u[s] = u;
@@ -322,16 +329,25 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
+        // t = T + D(k) with T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly
+        float thi[R], tlo[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int l3c = d + 2 * k0;
+            const int T = l3c * (l3c + 1) - gam[j];
+            thi[j] = (float)T;
+            tlo[j] = (float)(T - (int)thi[j]);
+        }
         const int kc_r = (kc + G - 1) / G * G;
+        const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
+        const float* ph = s_h + (R + 1) * lane + (R - 1);
         for (int sb = 0; sb < kc_r; sb += G) {
             float bt[R], bte[R], bee[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) bt[j] = bte[j] = bee[j] = 0.0f;
 #pragma unroll
-            for (int q = 0; q < G / R; ++q) {
+            for (int q = 0; q < G / R; ++q, pg -= R + 1, ph += R + 1) {
                 const int s0 = sb + q * R;
-                const float* pg = s_g + (R + 1) * (lane + (KC - s0) / R - 1) + (R - 1);
-                const float* ph = s_h + (R + 1) * (lane + s0 / R) + (R - 1);
                 const float4* pu = s_u + s0;
 #pragma unroll
                 for (int u = 0; u < R; ++u) {
@@ -342,13 +358,12 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
                     hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
                     const float4 uu = pu[u];
-                    const int c = __float_as_int(uu.w);
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const float P = gw[j] * hw[j];
                         bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
                         if (POL) {
-                            const float t = (float)(c - gam[j]);
+                            const float t = thi[j] + (uu.w + tlo[j]);
                             const float N = __builtin_fmaf(t, t, -beta[j]);
                             const float y = P * N;
                             bte[j] = __builtin_fmaf(uu.y, y, bte[j]);

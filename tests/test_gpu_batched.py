@@ -113,3 +113,64 @@ def test_batched_errors(torch_gpu, ctx):
             couple.couple_matrix_batched(fresh, [40], w, None, None, spectra=("TT",), precision="mfma_fp32")
     finally:
         couple.couple_free(fresh)
+
+
+def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk):
+    """Every tile shape gives a result within the bar; the autotuner keeps one of them."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [300, 77, 1, 190]
+    Ws = _rand_windows(lmaxes, 21)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    refs = [oracle_bulk.coupling_rows(L, *Ws[m], spectra=SPEC4) for m, L in enumerate(lmaxes)]
+    saved = couple.couple_get_batched_tiles(ctx)
+    try:
+        for tm in (1, 2, 4):
+            for fl in (1, 4, 8, 16):
+                couple.couple_set_batched_tiles(ctx, tm, fl)
+                outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32")
+                for m in range(len(lmaxes)):
+                    K = outs[m].cpu().numpy()
+                    for i, s in enumerate(SPEC4):
+                        assert_parity(K[i], refs[m][0][i], refs[m][1][i], TOL_MFMA, "tm %d flush %d %s" % (tm, fl, s))
+        tm, fl, ms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2])
+        assert tm in (1, 2, 4) and fl in (4, 8) and ms > 0
+        assert couple.couple_get_batched_tiles(ctx) == (tm, fl)
+        _say("autotune picked row_tiles=%d flush=%d (%.3f ms)" % (tm, fl, ms))
+        with pytest.raises(couple.CoupleError):
+            couple.couple_set_batched_tiles(ctx, 3, 8)
+    finally:
+        couple.couple_set_batched_tiles(ctx, *saved)
+
+
+def test_batched_graph_replay(torch_gpu, ctx):
+    """The batched call is capture-safe: a captured graph replays to the eager result,
+    replay after replay, with eager work in between."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [250, 64, 180]
+    Ws = _rand_windows(lmaxes, 33)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    eager = [o.clone() for o in couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2],
+                                                            precision="mfma_fp32")]
+    outs = [torch.empty_like(o) for o in eager]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32", outs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32", outs=outs)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        x = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")  # eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for m in range(len(lmaxes)):
+            assert torch.equal(outs[m], eager[m]), (rep, m)
+        del x
