@@ -89,12 +89,59 @@ def run_extras(torch, couple, synth, args):
     outs = [torch.empty((4, L + 1, L + 1), dtype=torch.float64, device="cuda") for L in lmaxes]
     couple.couple_reserve_batched(ctx, lmaxes)
     n_el = sum(4 * (L + 1) ** 2 for L in lmaxes)
-    for prec in ("mfma_fp32", "fp32c"):
-        ms = _timed(torch, lambda: couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=prec,
-                                                                outs=outs), steps, warm)
-        out["batched32_lmax500to4000_" + prec] = {"ms_per_call": ms, "k_elements_per_s": n_el / (ms * 1e-3),
-                                                   "masks": len(lmaxes), "elements": n_el}
-        print("[bench] batched %s: %.3f ms/call" % (prec, ms), file=sys.stderr, flush=True)
+    # useful contraction FLOP: 2 per (pair, l3, mask, spectrum) over TT/TE/EE, each mask at its own lmax
+    contraction = sum(2 * 3 * triples(L) for L in lmaxes)
+    check_rows = None
+    if not args.no_check:
+        from oracle import bulk
+        check_rows = [np.array(sorted({2, L // 2, L})) for L in lmaxes]
+        refs = [bulk.coupling_rows(L, *Ws[m], rows=check_rows[m], spectra=("TT", "TE", "EE", "BB"))
+                for m, L in enumerate(lmaxes)]
+    for prec in ("mfma_fp32", "mfma_bf16x3", "fp32c"):
+        call = lambda: couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=prec, outs=outs)
+        r = {"masks": len(lmaxes), "elements": n_el}
+        if prec.startswith("mfma"):
+            tm, fl, tms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2], outs=outs,
+                                                         precision=prec)
+            r["tiles"] = {"row_tiles": tm, "flush": fl, "autotune_ms": tms}
+        ms = _timed(torch, call, steps, warm)
+        r.update({"ms_per_call": ms, "k_elements_per_s": n_el / (ms * 1e-3)})
+        if prec.startswith("mfma"):
+            couple.couple_profile(ctx, True)
+            call()
+            prof = couple.couple_profile_read(ctx)
+            couple.couple_profile(ctx, False)
+            r["kernel_ms"] = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
+            peak = 157.3 if prec == "mfma_fp32" else 2500.0 / 3.0   # BF16x3: three bf16 products per FLOP
+            r["contraction_tflops"] = contraction / (r["kernel_ms"]["strip"] * 1e-3) / 1e12
+            r["contraction_peak_tflops"] = peak
+            # one captured graph per call: wprep, contraction, fill replayed without host launch work
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                call()
+            torch.cuda.current_stream().wait_stream(side)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                call()
+            r["graph_ms_per_call"] = _timed(torch, graph.replay, steps, warm)
+            del graph
+        if check_rows is not None:
+            call()
+            torch.cuda.synchronize()
+            errs = {}
+            for m in range(len(lmaxes)):
+                K = outs[m][:, torch.as_tensor(check_rows[m].astype(np.int64)).cuda(), :].cpu().numpy()
+                Kr, Ar = refs[m]
+                for i, s in enumerate(("TT", "TE", "EE", "BB")):
+                    nz = Ar[i] > 0
+                    e = float(np.max(np.abs(K[i][nz] - Kr[i][nz]) / Ar[i][nz]))
+                    errs[s] = max(errs.get(s, 0.0), e)
+            r["max_rel_err"] = errs
+            r["checked"] = "rows 2, lmax/2, lmax of every mask against the oracle"
+        out["batched32_lmax500to4000_" + prec] = r
+        print("[bench] batched %s: %.3f ms/call %s" % (prec, ms, r.get("max_rel_err", "")), file=sys.stderr,
+              flush=True)
     couple.couple_free(ctx)
     return out
 

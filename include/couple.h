@@ -58,8 +58,13 @@ enum couple_precision {
     COUPLE_FP64 = 0,   /* float64 throughout                                          */
     COUPLE_FP32C = 1,  /* float32 terms with compensated accumulation; float64 tables,
                           window scaling and final rescale                             */
-    COUPLE_MFMA_FP32 = 2 /* batched form only: float32 matrix-core contraction of the
-                            3j^2 tiles against the windows, Kahan-flushed accumulators */
+    COUPLE_MFMA_FP32 = 2, /* batched form only: float32 matrix-core contraction of the
+                             3j^2 tiles against the windows, Kahan-flushed accumulators */
+    COUPLE_MFMA_BF16X3 = 3 /* batched form only: the same contraction on bfloat16
+                              matrix cores with both operands split hi + lo and three
+                              products (hi*hi + hi*lo + lo*hi) accumulated in float32;
+                              relative error per term at most 3 * 2^-16 (4.6e-5),
+                              bfloat16 keeping 8 significant bits                */
 };
 
 /*
@@ -147,8 +152,10 @@ int couple_band_batched(couple_ctx *ctx, int n_masks, int l3_lo, int l3_hi, cons
  * of n_masks windows with the given lmax (HOST array).  Allocates (this is the
  * one entry point besides couple_init that does); later batched calls of the
  * same or smaller size allocate nothing.  Synchronises the device when the
- * workspace grows.  Size: per group of 16 masks (sorted by lmax, L = the
- * group's largest), 3 (L+1)(L+2)/2 x 16 float64 plus 3 (2L+1) x 16 float32.
+ * workspace grows.  Size: 3 (lmax_m+1)(lmax_m+2)/2 float64 per mask (its Xi),
+ * plus, per group of 16 masks sorted by lmax (L = the group's largest), the
+ * larger of the two W' tables: 3 (2L+33) x 16 float32 or
+ * 3 x 2 x 2 x 16 x (L+96 rounded up to 8) bfloat16.
  * Errors: EINVAL (NULL ctx/lmax_i, n_masks outside [1, 64], lmax > lmax_max),
  * ENOMEM.
  */
@@ -163,10 +170,13 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *   out             : HOST array of n_masks DEVICE float64 pointers; mask m
  *                     gets popcount(spectra) (lmax_i[m]+1)^2 entries in the
  *                     couple_matrix layout.
- *   precision       : COUPLE_MFMA_FP32 -- one launch for the whole batch: masks
- *                     sorted by lmax in groups of 16 sharing every generated
+ *   precision       : COUPLE_MFMA_FP32 or COUPLE_MFMA_BF16X3 -- one
+ *                     contraction launch for the whole batch (plus a window
+ *                     table kernel before and one fill kernel after): masks
+ *                     sorted by lmax in groups of 16 share every generated
  *                     3j^2 tile on the matrix cores; needs
- *                     couple_reserve_batched first.
+ *                     couple_reserve_batched first.  No allocation, no host
+ *                     synchronisation: the call can be captured in a graph.
  *                     COUPLE_FP64 / COUPLE_FP32C -- couple_matrix per mask.
  * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),
  * EDEVICE.
@@ -176,24 +186,27 @@ int couple_matrix_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const
                           unsigned spectra, int precision, double *const *out, void *stream);
 
 /*
- * Tile shape of the batched matrix-core kernel (COUPLE_MFMA_FP32):
- * row_tiles 16-row tiles of one diagonal per wavefront (1, 2 or 4) and the
- * number of 4-k MFMA steps between Kahan flushes of the float32 matrix-core
- * accumulators (1..16; fewer flushes are faster, more accurate the fewer
- * steps).  Defaults: 2 and 8.
+ * Tile shape of a batched matrix-core kernel (precision COUPLE_MFMA_FP32 or
+ * COUPLE_MFMA_BF16X3, each keeps its own): row_tiles 16-row tiles of one
+ * diagonal per wavefront (1, 2 or 4) and the number of MFMA steps between
+ * Kahan flushes of the float32 matrix-core accumulators (1..16; a float32
+ * step covers 4 l3 values, a BF16x3 step 32).  Defaults: float32 (2, 8),
+ * BF16x3 (2, 2).
  *
- * couple_autotune_batched times every (row_tiles in {1,2,4}, flush in {4,8})
- * on the given batch (same arguments as couple_matrix_batched; out is
- * overwritten), keeps the fastest in ctx for later batched calls and returns
- * it through the optional HOST pointers.  Synchronises the stream.
- * Errors: as couple_matrix_batched; EINVAL for a bad tile shape.
+ * couple_autotune_batched times every row_tiles in {1,2,4} with flush in
+ * {4,8} (float32) or {1,2} (BF16x3) on the given batch (same arguments as
+ * couple_matrix_batched; out is overwritten), keeps the fastest in ctx for
+ * later batched calls of that precision and returns it through the optional
+ * HOST pointers.  Synchronises the stream.
+ * Errors: as couple_matrix_batched; EINVAL for a bad tile shape or a
+ * precision without one.
  */
-int couple_set_batched_tiles(couple_ctx *ctx, int row_tiles, int flush);
-int couple_get_batched_tiles(const couple_ctx *ctx, int *row_tiles, int *flush);
-int couple_autotune_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const double *const *W_TT,
-                            const double *const *W_TP, const double *const *W_PP, const int *w_len_i,
-                            unsigned spectra, double *const *out, void *stream, int *best_row_tiles,
-                            int *best_flush, float *best_ms);
+int couple_set_batched_tiles(couple_ctx *ctx, int precision, int row_tiles, int flush);
+int couple_get_batched_tiles(couple_ctx *ctx, int precision, int *row_tiles, int *flush);
+int couple_autotune_batched(couple_ctx *ctx, int precision, int n_masks, const int *lmax_i,
+                            const double *const *W_TT, const double *const *W_TP, const double *const *W_PP,
+                            const int *w_len_i, unsigned spectra, double *const *out, void *stream,
+                            int *best_row_tiles, int *best_flush, float *best_ms);
 
 /*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for

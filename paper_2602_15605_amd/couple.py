@@ -21,7 +21,7 @@ COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EDEVICE, COUPLE_ENOTSUP = 0, -1,
 TT, TE, EE, BB = 1, 2, 4, 8
 SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB}
 SPECTRUM_ORDER = ("TT", "TE", "EE", "BB")
-PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2}
+PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2, "mfma_bf16x3": 3}
 LMAX_LIMIT = 16384
 
 
@@ -61,11 +61,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_reserve_batched.restype = i
     lib.couple_matrix_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, u, i, vp, vp]
     lib.couple_matrix_batched.restype = i
-    lib.couple_set_batched_tiles.argtypes = [vp, i, i]
+    lib.couple_set_batched_tiles.argtypes = [vp, i, i, i]
     lib.couple_set_batched_tiles.restype = i
-    lib.couple_get_batched_tiles.argtypes = [vp, vp, vp]
+    lib.couple_get_batched_tiles.argtypes = [vp, i, vp, vp]
     lib.couple_get_batched_tiles.restype = i
-    lib.couple_autotune_batched.argtypes = [vp, i, vp, vp, vp, vp, vp, u, vp, vp, vp, vp, vp]
+    lib.couple_autotune_batched.argtypes = [vp, i, i, vp, vp, vp, vp, vp, u, vp, vp, vp, vp, vp]
     lib.couple_autotune_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
@@ -273,18 +273,23 @@ def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE",
     return outs
 
 
-def couple_set_batched_tiles(ctx, row_tiles: int, flush: int) -> None:
-    _check(load_library().couple_set_batched_tiles(ctx.handle, int(row_tiles), int(flush)), ctx)
+def _prec(precision):
+    return PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
 
 
-def couple_get_batched_tiles(ctx):
+def couple_set_batched_tiles(ctx, row_tiles: int, flush: int, precision="mfma_fp32") -> None:
+    _check(load_library().couple_set_batched_tiles(ctx.handle, _prec(precision), int(row_tiles), int(flush)), ctx)
+
+
+def couple_get_batched_tiles(ctx, precision="mfma_fp32"):
     tm, fl = ctypes.c_int(), ctypes.c_int()
-    _check(load_library().couple_get_batched_tiles(ctx.handle, ctypes.byref(tm), ctypes.byref(fl)), ctx)
+    _check(load_library().couple_get_batched_tiles(ctx.handle, _prec(precision), ctypes.byref(tm),
+                                                   ctypes.byref(fl)), ctx)
     return tm.value, fl.value
 
 
 def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE", "EE", "BB"), outs=None,
-                            stream=None):
+                            stream=None, precision="mfma_fp32"):
     """Time the batched kernel's tile shapes on this batch; keep and return the best
     as (row_tiles, flush, ms)."""
     import torch
@@ -302,7 +307,7 @@ def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE
     optr = (ctypes.c_void_p * n)(*[_dev_ptr(o, "out") for o in outs])
     tm, fl, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
     rc = load_library().couple_autotune_batched(
-        ctx.handle, n, lm.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs],
+        ctx.handle, _prec(precision), n, lm.ctypes.data, *[ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs],
         wl.ctypes.data, bits, ctypes.cast(optr, ctypes.c_void_p), _stream_handle(stream), ctypes.byref(tm),
         ctypes.byref(fl), ctypes.byref(ms))
     _check(rc, ctx)

@@ -12,20 +12,28 @@
 // masks the N dimension, so the contraction runs on the matrix cores:
 //
 //   * masks are sorted by lmax and split into column groups of 16;
-//   * one wavefront owns a diagonal d and TM*16 consecutive l1 of a group; per
-//     step of 4 k it generates its A elements on the VALU (one per lane and
-//     row tile, the v_mfma_f32_16x16x4f32 operand layout: lane l holds row
-//     l % 16, k offset l / 16) and issues 3*TM MFMAs against the W' tile
-//     (k x 16 masks, lane l holds k offset l / 16, mask l % 16), loaded from
-//     the L2-resident W' table two steps ahead of its use;
-//   * every kFlush MFMA steps the float32 matrix-core accumulators are added
-//     into Kahan (sum, compensation) pairs, which bounds the float32
-//     accumulation error to a few ulp per block;
-//   * Xi goes to a mask-interleaved packed triangle, Xi[d, l1][16], which the
-//     output tile of the MFMA (lane l holds rows 4 (l/16) + i, mask l % 16)
-//     writes in 128-byte rows.
-// A fill pass then writes each mask's K (mask-major; columns beyond a mask's
-// own lmax are not written).
+//   * one wavefront owns a diagonal d and TM*16 consecutive l1 of a group; it
+//     generates its A elements on the VALU (g/h windows and the per-k factors
+//     staged in LDS, as in the strip kernels) in the A-operand layout of the
+//     MFMA and contracts them against the W' tile (k x 16 masks) loaded from
+//     an L2-resident table two steps ahead of its use;
+//   * float32 form: v_mfma_f32_16x16x4f32 (lane l holds row l % 16, k offset
+//     l / 16 of A and k offset l / 16, mask l % 16 of B);
+//     BF16x3 form: v_mfma_f32_16x16x32_bf16 (lane l holds row l % 16,
+//     k offsets 8 (l / 16) .. + 7); every float32 operand is split into
+//     bfloat16 hi + lo and the product is hi*hi + hi*lo + lo*hi, three MFMAs
+//     accumulating in float32 (the dropped lo*lo and the two split residues
+//     bound the product's relative error by 3 * 2^-16, bfloat16 keeping 8
+//     significant bits);
+//   * every `flush` steps the float32 matrix-core accumulators are added into
+//     Kahan (sum, compensation) pairs;
+//   * each mask's Xi goes to its own packed triangle [3][tri(lmax_m)], the
+//     store layout of the single-mask path; the MFMA output tile (lane l holds
+//     rows 4 (l/16) + i, mask l % 16) writes 16 consecutive l1 of a mask in
+//     one 128-byte run.
+// A fill pass then writes each mask's K (the single-mask fill, one job per
+// mask, all masks in one launch).
+#include <algorithm>
 #include <type_traits>
 
 #include "couple_internal.hpp"
@@ -34,10 +42,18 @@ namespace couple {
 namespace {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 constexpr int kGroup = kMaskGroup;  // masks per MFMA column block
-constexpr int kBChunk = 64;         // k steps staged per chunk (multiple of 4)
 constexpr int kBThreads = 64;
+constexpr int kChunkF32 = 128;      // k staged per chunk: 32 float32 steps
+constexpr int kChunkBF16 = 256;     // 8 BF16x3 steps
+
+// Zero rows after the last l3 of the float32 W' table, so the prefetch of the
+// two steps past a wavefront's last one stays in bounds without a test.
+constexpr int kF32TailRows = 32;
 
 struct BatchArgs {
     int n_groups;
@@ -45,23 +61,26 @@ struct BatchArgs {
     int L[kMaxGroups];              // largest lmax in the group
     int n_items[kMaxGroups];        // work items of the group
     int bmax[kMaxGroups];
-    long long xi_off[kMaxGroups];   // offset of the group's Xi (doubles)
-    long long wt_off[kMaxGroups];   // offset of the group's W' table (floats)
+    long long wt_off[kMaxGroups];   // offset of the group's W' table (elements)
+    int wt_len[kMaxGroups];         // float32: rows 2L+1+tail; BF16x3: j slots per (x, piece, parity, mask)
+    // per mask of a group (lmax -1: empty column)
+    int lmax[kMaxGroups][kGroup];
+    long long xi_off[kMaxGroups][kGroup];   // offset of the mask's Xi store [3][tri(lmax)] (doubles)
     // shared
     const double* g;                // float64 g(p)
     const float* gf;                // float32 g(p)
     const float* hf;                // float32 1/((2p+1) g(p))
     const double* cl;
-    const float* wtab;              // W' tables, [3][2L+1][16] per group
+    const void* wtab;               // W' tables of every group
     double* xi;                     // Xi workspace base
     int g_len, h_len;
     int flush;                      // MFMA steps per Kahan flush
 };
 
-template <int TM>
+template <int TM, int KC>
 struct BWin {
     static constexpr int kRows = 16 * TM;
-    static constexpr int kLen = kRows + kBChunk + 3;
+    static constexpr int kLen = kRows + KC + 3;
 };
 
 // Kahan step: (s, c) += v.
@@ -72,18 +91,11 @@ __device__ inline void kahan_add(float& s, float& c, float v) {
     s = t;
 }
 
+// Work item -> (group, level b, diagonal d); items of a group are numbered
+// with the longest rows (largest b) first.
 template <int TM>
-__global__ void __launch_bounds__(kBThreads)
-batched_mfma_f32_kernel(BatchArgs a) {
-    using W = BWin<TM>;
-    constexpr int KC = kBChunk;
-    __shared__ float s_g[W::kLen];
-    __shared__ float s_h[W::kLen];
-    __shared__ float s_s[KC + 4];       // S(k) = g(k) g(d+k), float32
-    __shared__ float s_dc[KC + 4];      // D(k) = c(k) - c(chunk start), exact in float32
-
-    // ---- work item: group, then level b (descending), diagonal d ----
-    int item = blockIdx.x;
+__device__ inline void decode_item(const BatchArgs& a, int item, int* grp_out, int* b_out, int* d_out) {
+    constexpr int kRows = 16 * TM;
     int grp = 0;
     while (grp < a.n_groups - 1 && item >= a.n_items[grp]) {
         item -= a.n_items[grp];
@@ -92,26 +104,95 @@ batched_mfma_f32_kernel(BatchArgs a) {
     const int L = a.L[grp];
     int b = a.bmax[grp];
     for (; b > 0; --b) {
-        const int nb = L - W::kRows * b + 1;
+        const int nb = L - kRows * b + 1;
         if (nb > 0) {
             if (item < nb) break;
             item -= nb;
         }
     }
-    const int d = item;
-    const int A0 = W::kRows * b;
-    const int n_valid = L - d + 1;
-    const int kmax = min(A0 + W::kRows, n_valid) - 1;
+    *grp_out = grp;
+    *b_out = b;
+    *d_out = item;
+}
 
-    const int lane = threadIdx.x;
+// Stage the chunk of k = kch .. kch + KC - 1: the g / h windows of the
+// wavefront's rows, S(k) = g(k) g(d+k) (0 outside 0 <= k <= kmax) and
+// D(k) = c(d + 2k) - c(d + 2 kch), an integer exact in float32.  Fully
+// unrolled, so every global load is in flight before the first LDS write.
+template <int TM, int KC>
+__device__ inline void stage_chunk(const BatchArgs& a, float* s_g, float* s_h, float* s_s, float* s_dc, int A0,
+                                   int d, int kch, int kmax, int lane) {
+    using W = BWin<TM, KC>;
+    constexpr int NW = (W::kLen + kBThreads - 1) / kBThreads;
+    constexpr int NK = KC / kBThreads;
+    const int g_base = A0 - kch - KC - 3;
+    const int h_base = A0 + d + kch;
+    float gv[NW], hv[NW];
+    double ga[NK], gb[NK];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int slot = lane + kBThreads * i;
+        const int eg = g_base + slot, eh = h_base + slot;
+        gv[i] = (slot < W::kLen && eg >= 0 && eg < a.g_len) ? a.gf[eg] : 0.0f;
+        hv[i] = (slot < W::kLen && eh >= 0 && eh < a.h_len) ? a.hf[eh] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const int k = kch + lane + kBThreads * i;
+        const bool ok = k >= 0 && k <= kmax;
+        ga[i] = ok ? a.g[k] : 0.0;
+        gb[i] = ok ? a.g[d + k] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int slot = lane + kBThreads * i;
+        if (slot < W::kLen) {
+            s_g[slot] = gv[i];
+            s_h[slot] = hv[i];
+        }
+    }
+    const int l3c = d + 2 * kch;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const int s = lane + kBThreads * i;
+        const int k = kch + s;
+        const int l3 = d + 2 * k;
+        s_s[s] = (float)(ga[i] * gb[i]);
+        s_dc[s] = (k >= 0 && k <= kmax) ? (float)(l3 * (l3 + 1) - l3c * (l3c + 1)) : 0.0f;
+    }
+}
+
+// Xi store of the wavefront's rows: lane (r, q) holds rows 4q + i of each row
+// tile for mask r of the group.  The (-2 2 0) row factor s = c_l1 c_l2 / 2
+// (App. B.3) is applied here in float64.
+template <int TM>
+__device__ inline void store_xi(const BatchArgs& a, int grp, int d, int A0, int lane, const float (&ks)[TM][3][4],
+                                const float (&kc)[TM][3][4]) {
     const int r = lane & 15, q = lane >> 4;
-    const int wl = 2 * L + 1;
-    // B operand: W'_X(l3)[mask r] with l3 = d + 2k, k = 4 step + q
-    const float* wt = a.wtab + a.wt_off[grp] + r;
-    const long long xs = (long long)wl * kGroup;    // stride between spectra
+    const int lm = a.lmax[grp][r];
+    if (lm < d) return;
+    double* xi = a.xi + a.xi_off[grp][r];
+    const long long tri = tri_size(lm);
+    const long long off = diag_offset(lm, d);
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int l1 = A0 + 16 * t + 4 * q + i;
+            if (l1 <= lm - d) {
+                const double sp = 0.5 * a.cl[l1] * a.cl[l1 + d];
+                const long long idx = off + l1;
+                xi[idx] = (double)ks[t][0][i] - (double)kc[t][0][i];
+                xi[tri + idx] = sp * ((double)ks[t][1][i] - (double)kc[t][1][i]);
+                xi[2 * tri + idx] = (sp * sp) * ((double)ks[t][2][i] - (double)kc[t][2][i]);
+            }
+        }
+}
 
-    int gam[TM];
-    float beta[TM];
+// Row constants: gam = a + b - 1 (exact int) and beta = 2ab + 1 (float32),
+// with N' = t^2 - beta and t = c - gam.
+template <int TM>
+__device__ inline void row_constants(int A0, int d, int r, int (&gam)[TM], float (&beta)[TM]) {
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
         const long long l1 = A0 + 16 * t + r, l2 = l1 + d;
@@ -119,6 +200,51 @@ batched_mfma_f32_kernel(BatchArgs a) {
         gam[t] = (int)(aa + bb - 1);
         beta[t] = (float)(2.0 * (double)aa * (double)bb + 1.0);
     }
+}
+
+template <int TM>
+__device__ inline void flush_acc(f4v (&acc)[TM][3], float (&ks)[TM][3][4], float (&kc)[TM][3][4]) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) kahan_add(ks[t][x][i], kc[t][x][i], acc[t][x][i]);
+            acc[t][x] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+}
+
+// ---------------------------------------------------------------------------
+// float32 matrix-core form: steps of 4 k, lane k offset q = lane / 16.
+// W' table per group: [3][wt_len][16] float32, row l3, zero beyond 2 lmax_m
+// and in the tail rows.
+template <int TM>
+__global__ void __launch_bounds__(kBThreads)
+batched_mfma_f32_kernel(BatchArgs a) {
+    constexpr int KC = kChunkF32;
+    using W = BWin<TM, KC>;
+    __shared__ float s_g[W::kLen];
+    __shared__ float s_h[W::kLen];
+    __shared__ float s_s[KC];
+    __shared__ float s_dc[KC];
+
+    int grp, b, d;
+    decode_item<TM>(a, blockIdx.x, &grp, &b, &d);
+    const int L = a.L[grp];
+    const int A0 = W::kRows * b;
+    const int n_valid = L - d + 1;
+    const int kmax = min(A0 + W::kRows, n_valid) - 1;
+
+    const int lane = threadIdx.x;
+    const int r = lane & 15, q = lane >> 4;
+    // B operand: W'_X(l3)[mask r], l3 = d + 2k, k = 4 step + q; a step advances 8 rows
+    const float* pb = static_cast<const float*>(a.wtab) + a.wt_off[grp] + (long long)(d + 2 * q) * kGroup + r;
+    const long long xs = (long long)a.wt_len[grp] * kGroup;
+    constexpr int kStepRows = 8 * kGroup;
+
+    int gam[TM];
+    float beta[TM];
+    row_constants<TM>(A0, d, r, gam, beta);
     f4v acc[TM][3];
     float ks[TM][3][4], kc[TM][3][4];
 #pragma unroll
@@ -130,44 +256,23 @@ batched_mfma_f32_kernel(BatchArgs a) {
             for (int i = 0; i < 4; ++i) ks[t][x][i] = kc[t][x][i] = 0.0f;
         }
 
-    const int n_steps = (kmax + 4) / 4;          // steps of 4 k
-    // B prefetch two steps ahead (0 beyond the row or the window)
-    auto load_b = [&](int step, float* bv) {
-        const int l3 = d + 2 * (4 * step + q);
-        const bool ok = step < n_steps && l3 < wl;
-        const float* p = wt + (long long)l3 * kGroup;
-        bv[0] = ok ? p[0] : 0.0f;
-        bv[1] = ok ? p[xs] : 0.0f;
-        bv[2] = ok ? p[2 * xs] : 0.0f;
-    };
-    float b0[3], b1[3];
-    load_b(0, b0);
-    load_b(1, b1);
+    // two B buffers: even steps use bA, odd steps bB; each is refilled for the
+    // step two ahead right after its use
+    float bA[3], bB[3];
+    bA[0] = pb[0];
+    bA[1] = pb[xs];
+    bA[2] = pb[2 * xs];
+    bB[0] = pb[kStepRows];
+    bB[1] = pb[kStepRows + xs];
+    bB[2] = pb[kStepRows + 2 * xs];
+    pb += 2 * kStepRows;
 
     int since_flush = 0;
-    for (int k0 = 0; k0 <= kmax; k0 += KC) {
-        const int kc_n = min(KC, kmax - k0 + 1);
+    for (int kch = 0; kch <= kmax; kch += KC) {
+        const int kc_n = min(KC, kmax - kch + 1);
         __syncthreads();
-        const int g_base = A0 - k0 - KC - 3;
-        const int h_base = A0 + d + k0;
-        for (int slot = lane; slot < W::kLen; slot += kBThreads) {
-            const int eg = g_base + slot, eh = h_base + slot;
-            s_g[slot] = (eg >= 0 && eg < a.g_len) ? a.gf[eg] : 0.0f;
-            s_h[slot] = (eh >= 0 && eh < a.h_len) ? a.hf[eh] : 0.0f;
-        }
-        const int l3c = d + 2 * k0;
-        for (int s = lane; s < KC + 4; s += kBThreads) {
-            float sv = 0.0f, dv = 0.0f;
-            if (s < kc_n) {
-                const int k = k0 + s;
-                sv = (float)(a.g[k] * a.g[d + k]);
-                const int l3 = d + 2 * k;
-                dv = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
-            }
-            s_s[s] = sv;
-            s_dc[s] = dv;
-        }
-        // t = T + D(k), T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly
+        stage_chunk<TM, KC>(a, s_g, s_h, s_s, s_dc, A0, d, kch, kmax, lane);
+        const int l3c = d + 2 * kch;
         float thi[TM], tlo[TM];
 #pragma unroll
         for (int t = 0; t < TM; ++t) {
@@ -176,219 +281,313 @@ batched_mfma_f32_kernel(BatchArgs a) {
             tlo[t] = (float)(T - (int)thi[t]);
         }
         __syncthreads();
+        const int g_base = A0 - kch - KC - 3;
 
-        for (int s0 = 0; s0 < kc_n; s0 += 4) {
-            const int s = s0 + q;                 // this lane's k offset in the chunk
+        auto step = [&](int s0, float (&bv)[3]) {
+            const int s = s0 + q;
             const float S = s_s[s];
             const float D = s_dc[s];
-            const float btt = b0[0], btp = b0[1], bpp = b0[2];
-            b0[0] = b1[0];
-            b0[1] = b1[1];
-            b0[2] = b1[2];
-            load_b((k0 + s0) / 4 + 2, b1);
+            float x2[TM], y[TM], z[TM];
 #pragma unroll
             for (int t = 0; t < TM; ++t) {
                 const int l1 = A0 + 16 * t + r;
-                const float gv = s_g[l1 - (k0 + s) - g_base];
+                const float gv = s_g[l1 - (kch + s) - g_base];
                 const float hv = s_h[l1 - A0 + s];
-                const float x2 = S * (gv * hv);
+                x2[t] = S * (gv * hv);
                 const float tt = thi[t] + (D + tlo[t]);
                 const float N = __builtin_fmaf(tt, tt, -beta[t]);
-                const float y = x2 * N;
-                const float z = y * N;
-                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2, btt, acc[t][0], 0, 0, 0);
-                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(y, btp, acc[t][1], 0, 0, 0);
-                acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(z, bpp, acc[t][2], 0, 0, 0);
+                y[t] = x2[t] * N;
+                z[t] = y[t] * N;
             }
+#pragma unroll
+            for (int t = 0; t < TM; ++t) {
+                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2[t], bv[0], acc[t][0], 0, 0, 0);
+                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[t], bv[1], acc[t][1], 0, 0, 0);
+                acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[t], bv[2], acc[t][2], 0, 0, 0);
+            }
+            bv[0] = pb[0];
+            bv[1] = pb[xs];
+            bv[2] = pb[2 * xs];
+            pb += kStepRows;
             if (++since_flush >= a.flush) {
                 since_flush = 0;
-#pragma unroll
-                for (int t = 0; t < TM; ++t)
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) kahan_add(ks[t][x][i], kc[t][x][i], acc[t][x][i]);
-                        acc[t][x] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-                    }
+                flush_acc<TM>(acc, ks, kc);
             }
+        };
+        // KC is a multiple of 8, so every chunk starts on an even step
+        for (int s0 = 0; s0 < kc_n; s0 += 8) {
+            step(s0, bA);
+            if (s0 + 4 < kc_n) step(s0 + 4, bB);
         }
     }
+    flush_acc<TM>(acc, ks, kc);
+    store_xi<TM>(a, grp, d, A0, lane, ks, kc);
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 matrix-core form: steps of 32 k, lane k offsets 8q .. 8q + 7.
+//
+// The k origin is shifted so that j = (l3 - p) / 2 (p = d mod 2) of every
+// lane's first k is a multiple of 8: the W' table per group is
+// [3][2 pieces (hi, lo)][2 parities][16 masks][wt_len j slots] bfloat16, and
+// a lane's 8 values of one (spectrum, piece) are one aligned 16-byte load.
+// k < 0 and k > kmax contribute 0 through S(k) = 0.
+
+// v -> (hi, lo) bfloat16 with hi = RN(v), lo = RN(v - hi): 8 values, packed
+// two at a time by v_cvt_pk_bf16_f32; float(hi) is read back from the bits.
+__device__ inline void split_bf16(const float (&v)[8], bf8v& hi, bf8v& lo) {
 #pragma unroll
-    for (int t = 0; t < TM; ++t)
+    for (int e = 0; e < 8; e += 2) {
+        const bf2v h = {(__bf16)v[e], (__bf16)v[e + 1]};
+        const unsigned hb = __builtin_bit_cast(unsigned, h);
+        const float f0 = __builtin_bit_cast(float, hb << 16);
+        const float f1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+        const bf2v l = {(__bf16)(v[e] - f0), (__bf16)(v[e + 1] - f1)};
+        hi[e] = h[0];
+        hi[e + 1] = h[1];
+        lo[e] = l[0];
+        lo[e + 1] = l[1];
+    }
+}
+
+struct BTile {
+    bf8v v[3][2];    // [spectrum][hi, lo]
+};
+
+template <int TM>
+__global__ void __launch_bounds__(kBThreads)
+batched_mfma_bf16x3_kernel(BatchArgs a) {
+    constexpr int KC = kChunkBF16;  // a multiple of two steps of 32 k
+    using W = BWin<TM, KC>;
+    __shared__ float s_g[W::kLen];
+    __shared__ float s_h[W::kLen];
+    __shared__ __attribute__((aligned(16))) float s_s[KC];
+    __shared__ __attribute__((aligned(16))) float s_dc[KC];
+
+    int grp, b, d;
+    decode_item<TM>(a, blockIdx.x, &grp, &b, &d);
+    const int L = a.L[grp];
+    const int A0 = W::kRows * b;
+    const int n_valid = L - d + 1;
+    const int kmax = min(A0 + W::kRows, n_valid) - 1;
+
+    const int lane = threadIdx.x;
+    const int r = lane & 15, q = lane >> 4;
+    const int p = d & 1, jd = (d - p) >> 1;
+    const int k_org = -(jd & 7);                 // first k: j = jd + k_org is a multiple of 8
+    const int jn = a.wt_len[grp];                // a multiple of 8
+    const __bf16* base = static_cast<const __bf16*>(a.wtab) + a.wt_off[grp] +
+                         (long long)(p * kGroup + r) * jn + (jd + k_org) + 8 * q;
+    const u4v* pb = reinterpret_cast<const u4v*>(base);
+    const long long xpv = 2LL * kGroup * jn / 8;  // stride between (spectrum, piece) blocks, 16-byte units
+
+    auto load_b = [&](BTile& bt) {
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) kahan_add(ks[t][x][i], kc[t][x][i], acc[t][x][i]);
+            for (int h = 0; h < 2; ++h) bt.v[x][h] = __builtin_bit_cast(bf8v, pb[(2 * x + h) * xpv]);
+        pb += 4;                                  // 32 j
+    };
 
-    // ---- store: lane holds rows 4q + i of each row tile, mask column r ----
-    const long long tri = (long long)(L + 1) * (L + 2) / 2;
-    double* xi = a.xi + a.xi_off[grp];
-    const long long off = diag_offset(L, d);
+    int gam[TM];
+    float beta[TM];
+    row_constants<TM>(A0, d, r, gam, beta);
+    f4v acc[TM][3];
+    float ks[TM][3][4], kc[TM][3][4];
 #pragma unroll
     for (int t = 0; t < TM; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int l1 = A0 + 16 * t + 4 * q + i;
-            if (l1 < n_valid) {
-                const double sp = 0.5 * a.cl[l1] * a.cl[l1 + d];
-                const long long idx = (off + l1) * kGroup + r;
-                xi[idx] = (double)ks[t][0][i] - (double)kc[t][0][i];
-                xi[tri * kGroup + idx] = sp * ((double)ks[t][1][i] - (double)kc[t][1][i]);
-                xi[2 * tri * kGroup + idx] = (sp * sp) * ((double)ks[t][2][i] - (double)kc[t][2][i]);
-            }
+        for (int x = 0; x < 3; ++x) {
+            acc[t][x] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ks[t][x][i] = kc[t][x][i] = 0.0f;
         }
+
+    BTile bA, bB;
+    load_b(bA);
+    load_b(bB);
+
+    int since_flush = 0;
+    for (int kch = k_org; kch <= kmax; kch += KC) {
+        __syncthreads();
+        stage_chunk<TM, KC>(a, s_g, s_h, s_s, s_dc, A0, d, kch, kmax, lane);
+        const int l3c = d + 2 * kch;
+        float thi[TM], tlo[TM];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+            const int T = l3c * (l3c + 1) - gam[t];
+            thi[t] = (float)T;
+            tlo[t] = (float)(T - (int)thi[t]);
+        }
+        __syncthreads();
+        const int g_base = A0 - kch - KC - 3;
+
+        auto step = [&](int s0, BTile& bt) {
+            const int sb = s0 + 8 * q;               // this lane's first k offset in the chunk
+            float S[8], D[8];
+            {
+                const f4v s0v = *reinterpret_cast<const f4v*>(&s_s[sb]);
+                const f4v s1v = *reinterpret_cast<const f4v*>(&s_s[sb + 4]);
+                const f4v d0v = *reinterpret_cast<const f4v*>(&s_dc[sb]);
+                const f4v d1v = *reinterpret_cast<const f4v*>(&s_dc[sb + 4]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    S[e] = s0v[e];
+                    S[e + 4] = s1v[e];
+                    D[e] = d0v[e];
+                    D[e + 4] = d1v[e];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TM; ++t) {
+                const int l1 = A0 + 16 * t + r;
+                const float* pg = &s_g[l1 - (kch + sb) - g_base];
+                const float* ph = &s_h[l1 - A0 + sb];
+                // one spectrum at a time: x2, then y = x2 N', then z = y N', each
+                // split and contracted (hi*hi, hi*lo, lo*hi) before the next
+                float v[8], N[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    v[e] = S[e] * (pg[-e] * ph[e]);
+                    const float tt = thi[t] + (D[e] + tlo[t]);
+                    N[e] = __builtin_fmaf(tt, tt, -beta[t]);
+                }
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    if (x > 0) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) v[e] *= N[e];
+                    }
+                    bf8v ah, al;
+                    split_bf16(v, ah, al);
+                    acc[t][x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bt.v[x][0], acc[t][x], 0, 0, 0);
+                    acc[t][x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bt.v[x][1], acc[t][x], 0, 0, 0);
+                    acc[t][x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bt.v[x][0], acc[t][x], 0, 0, 0);
+                }
+            }
+            load_b(bt);
+            if (++since_flush >= a.flush) {
+                since_flush = 0;
+                flush_acc<TM>(acc, ks, kc);
+            }
+        };
+        // KC is a multiple of 64, so every chunk starts on an even step
+        for (int s0 = 0; s0 < KC && kch + s0 <= kmax; s0 += 64) {
+            step(s0, bA);
+            if (kch + s0 + 32 <= kmax) step(s0 + 32, bB);
+        }
+    }
+    flush_acc<TM>(acc, ks, kc);
+    store_xi<TM>(a, grp, d, A0, lane, ks, kc);
 }
 
-// W' tables of every group: [3][2L+1][16] float32, (2l+1) W_l / 4 pi rounded once.
+// ---------------------------------------------------------------------------
+// W' tables of every group, (2l+1) W_l / 4 pi rounded once from float64.
 struct WPrepArgs {
     int n_groups;
-    int L[kMaxGroups];
+    int bf16;                       // 0: float32 table, 1: BF16x3 table
+    int wt_len[kMaxGroups];
     long long wt_off[kMaxGroups];
+    long long n_elem[kMaxGroups];   // float32 entries, or BF16x3 (spectrum, parity, mask, j) slots
     int n_masks[kMaxGroups];
     int lmax[kMaxGroups][kGroup];
     const double* w[kMaxGroups][3][kGroup];
-    float* wtab;
+    void* wtab;
 };
 
 constexpr double kInv4PiB = 0.079577471545947667884441881686257181;
 
+__device__ inline double wprime(const WPrepArgs& a, int grp, int x, int m, int l) {
+    if (m >= a.n_masks[grp] || l > 2 * a.lmax[grp][m] || !a.w[grp][x][m]) return 0.0;
+    return a.w[grp][x][m][l] * ((2.0 * l + 1.0) * kInv4PiB);
+}
+
 __global__ void batched_wprep_kernel(WPrepArgs a) {
     const int grp = blockIdx.y;
     if (grp >= a.n_groups) return;
-    const int wl = 2 * a.L[grp] + 1;
-    float* wt = a.wtab + a.wt_off[grp];
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 3LL * wl * kGroup;
+    const int len = a.wt_len[grp];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem[grp];
          e += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(e / ((long long)wl * kGroup));
-        const int rem = (int)(e % ((long long)wl * kGroup));
-        const int l = rem / kGroup, m = rem % kGroup;
-        float v = 0.0f;
-        if (m < a.n_masks[grp] && l <= 2 * a.lmax[grp][m] && a.w[grp][x][m])
-            v = (float)(a.w[grp][x][m][l] * ((2.0 * l + 1.0) * kInv4PiB));
-        wt[e] = v;
-    }
-}
-
-// K of every mask from the mask-interleaved Xi: one work-group per (group
-// tile pair, mask); the tile is read diagonal by diagonal and written row by
-// row and mirrored, as in fill_kernel.
-struct BFillArgs {
-    int n_groups;
-    int L[kMaxGroups];
-    long long xi_off[kMaxGroups];
-    int n_masks[kMaxGroups];
-    int lmax[kMaxGroups][kGroup];
-    double* out[kMaxGroups][kGroup];
-    int n_tiles[kMaxGroups];
-    long long pair_base[kMaxGroups];    // first block index of the group
-    const double* xi;
-    int n_out;
-    int src[4];
-};
-
-constexpr int kT = 64;
-
-__global__ void __launch_bounds__(256) batched_fill_kernel(BFillArgs a) {
-    __shared__ double tile[kT][kT + 1];
-    long long blk = blockIdx.x;
-    int grp = 0;
-    while (grp < a.n_groups - 1 && blk >= a.pair_base[grp + 1]) ++grp;
-    blk -= a.pair_base[grp];
-    const int m = (int)(blk % kGroup);
-    const int pair = (int)(blk / kGroup);
-    if (m >= a.n_masks[grp]) return;
-    const int lmax = a.lmax[grp][m];
-    int I = 0, rem = pair;
-    const int nt = a.n_tiles[grp];
-    while (rem >= nt - I) {
-        rem -= nt - I;
-        ++I;
-    }
-    const int J = I + rem;
-    const int r0 = kT * I, c0 = kT * J;
-    if (r0 > lmax || c0 > lmax) return;
-    const int L = a.L[grp];
-    const long long tri = (long long)(L + 1) * (L + 2) / 2;
-    const double* xi = a.xi + a.xi_off[grp];
-    const int t = threadIdx.x;
-    const long long ld = lmax + 1;
-    int last_src = -1;
-    for (int o = 0; o < a.n_out; ++o) {
-        const int src = a.src[o];
-        if (src != last_src) {
-            __syncthreads();
-            for (int idx = t; idx < (2 * kT - 1) * kT; idx += 256) {
-                const int rr = idx % kT, dl = idx / kT;
-                const int cc = rr + dl - (kT - 1);
-                if (cc < 0 || cc >= kT) continue;
-                const int l1 = r0 + rr, l2 = c0 + cc;
-                if (l1 > lmax || l2 > lmax || l2 < l1) continue;
-                tile[rr][cc] = xi[((long long)src * tri + diag_offset(L, l2 - l1) + l1) * kGroup + m];
-            }
-            __syncthreads();
-            last_src = src;
-        }
-        double* out = a.out[grp][m] + (long long)o * ld * ld;
-        if (I == J) {
-            for (int idx = t; idx < kT * kT; idx += 256) {
-                const int rr = idx / kT, cc = idx % kT;
-                const int l1 = r0 + rr, l2 = c0 + cc;
-                if (l1 > lmax || l2 > lmax) continue;
-                out[l1 * ld + l2] = (2.0 * l2 + 1.0) * ((cc >= rr) ? tile[rr][cc] : tile[cc][rr]);
-            }
+        if (!a.bf16) {
+            // [x][l3][m]
+            const int x = (int)(e / ((long long)len * kGroup));
+            const int rem = (int)(e % ((long long)len * kGroup));
+            const int l = rem / kGroup, m = rem % kGroup;
+            static_cast<float*>(a.wtab)[a.wt_off[grp] + e] = (float)wprime(a, grp, x, m, l);
         } else {
-            for (int idx = t; idx < kT * kT; idx += 256) {
-                const int rr = idx / kT, cc = idx % kT;
-                const int l1 = r0 + rr, l2 = c0 + cc;
-                if (l1 <= lmax && l2 <= lmax) out[l1 * ld + l2] = (2.0 * l2 + 1.0) * tile[rr][cc];
-            }
-            for (int idx = t; idx < kT * kT; idx += 256) {
-                const int cc = idx / kT, rr = idx % kT;
-                const int l1 = r0 + rr, l2 = c0 + cc;
-                if (l1 <= lmax && l2 <= lmax) out[l2 * ld + l1] = (2.0 * l1 + 1.0) * tile[rr][cc];
-            }
+            // slot e = ((x * 2 + p) * 16 + m) * len + j, l3 = p + 2 j; pieces hi / lo
+            // go to blocks 2x and 2x + 1 of [6][2][16][len]
+            const int j = (int)(e % len);
+            const long long rest = e / len;
+            const int m = (int)(rest % kGroup);
+            const int p = (int)((rest / kGroup) % 2);
+            const int x = (int)(rest / (2 * kGroup));
+            const float v = (float)wprime(a, grp, x, m, p + 2 * j);
+            const __bf16 hi = (__bf16)v;
+            const __bf16 lo = (__bf16)(v - (float)hi);
+            __bf16* t = static_cast<__bf16*>(a.wtab) + a.wt_off[grp];
+            const long long inner = ((long long)p * kGroup + m) * len + j;
+            const long long blk = 2LL * kGroup * len;
+            t[(2LL * x) * blk + inner] = hi;
+            t[(2LL * x + 1) * blk + inner] = lo;
         }
     }
 }
+
+// Table geometry of a group of largest lmax L.
+inline int f32_rows(int L) { return 2 * L + 1 + kF32TailRows; }
+// A wavefront's last executed step starts at j <= jd + kmax <= L ((l3 - p) / 2 for
+// l3 <= 2L) and it has loaded the two steps after it: j <= L + 95.  A multiple of 8.
+inline int bf16_slots(int L) { return ((L + 96 + 7) / 8) * 8; }
+inline size_t f32_table_elems(int L) { return 3ULL * (size_t)f32_rows(L) * kGroup; }
+inline size_t bf16_table_elems(int L) { return 3ULL * 2 * 2 * kGroup * (size_t)bf16_slots(L); }
 
 }  // namespace
 
 size_t batched_workspace_bytes(const BatchPlan& p) {
-    size_t doubles = 0, floats = 0;
+    size_t xi = 0, f32 = 0, bf = 0;
     for (int gi = 0; gi < p.n_groups; ++gi) {
-        const long long L = p.L[gi];
-        doubles += 3ULL * (size_t)((L + 1) * (L + 2) / 2) * kGroup;
-        floats += 3ULL * (size_t)(2 * L + 1) * kGroup;
+        for (int m = 0; m < p.n_masks[gi]; ++m) xi += 3ULL * (size_t)tri_size(p.lmax[gi][m]);
+        f32 += f32_table_elems(p.L[gi]);
+        bf += bf16_table_elems(p.L[gi]);
     }
-    return doubles * sizeof(double) + floats * sizeof(float) + 256;
+    // Xi (float64), then one 256-byte aligned W' table region large enough for either form
+    const size_t tab = std::max(f32 * sizeof(float), bf * sizeof(__bf16));
+    return xi * sizeof(double) + tab + 256;
 }
 
 hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, const int* spec_src, int n_out,
                           hipStream_t s) {
-    (void)precision;
+    const bool bf16 = precision == COUPLE_MFMA_BF16X3;
     double* xi = reinterpret_cast<double*>(ctx->bws);
+    long long xi_off[kMaxGroups][kGroup];
     size_t xi_doubles = 0;
-    long long xi_off[kMaxGroups], wt_off[kMaxGroups];
-    size_t wt_floats = 0;
+    for (int gi = 0; gi < kMaxGroups; ++gi)
+        for (int m = 0; m < kGroup; ++m) {
+            xi_off[gi][m] = (long long)xi_doubles;
+            if (gi < p.n_groups && m < p.n_masks[gi]) xi_doubles += 3ULL * (size_t)tri_size(p.lmax[gi][m]);
+        }
+    void* wtab = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(xi + xi_doubles) + 255) &
+                                         ~static_cast<uintptr_t>(255));
+    long long wt_off[kMaxGroups];
+    int wt_len[kMaxGroups];
+    long long off = 0;
     for (int gi = 0; gi < p.n_groups; ++gi) {
-        const long long L = p.L[gi];
-        xi_off[gi] = (long long)xi_doubles;
-        xi_doubles += 3ULL * (size_t)((L + 1) * (L + 2) / 2) * kGroup;
+        wt_off[gi] = off;
+        wt_len[gi] = bf16 ? bf16_slots(p.L[gi]) : f32_rows(p.L[gi]);
+        off += (long long)(bf16 ? bf16_table_elems(p.L[gi]) : f32_table_elems(p.L[gi]));
     }
-    for (int gi = 0; gi < p.n_groups; ++gi) {
-        wt_off[gi] = (long long)wt_floats;
-        wt_floats += 3ULL * (size_t)(2 * p.L[gi] + 1) * kGroup;
-    }
-    float* wtab = reinterpret_cast<float*>(xi + xi_doubles);
 
     // W' tables
     {
         WPrepArgs w;
         w.n_groups = p.n_groups;
+        w.bf16 = bf16 ? 1 : 0;
         w.wtab = wtab;
         for (int gi = 0; gi < p.n_groups; ++gi) {
-            w.L[gi] = p.L[gi];
+            w.wt_len[gi] = wt_len[gi];
             w.wt_off[gi] = wt_off[gi];
+            w.n_elem[gi] = bf16 ? 3LL * 2 * kGroup * wt_len[gi] : (long long)f32_table_elems(p.L[gi]);
             w.n_masks[gi] = p.n_masks[gi];
             for (int m = 0; m < kGroup; ++m) {
                 w.lmax[gi][m] = m < p.n_masks[gi] ? p.lmax[gi][m] : -1;
@@ -419,8 +618,12 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
             }
             a.n_items[gi] = (int)n;
             total += n;
-            a.xi_off[gi] = xi_off[gi];
             a.wt_off[gi] = wt_off[gi];
+            a.wt_len[gi] = wt_len[gi];
+            for (int m = 0; m < kGroup; ++m) {
+                a.lmax[gi][m] = m < p.n_masks[gi] ? p.lmax[gi][m] : -1;
+                a.xi_off[gi][m] = xi_off[gi][m];
+            }
         }
         a.g = ctx->g_pad + kTablePad;
         a.gf = ctx->gf_pad + kTablePad;
@@ -430,9 +633,12 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
         a.xi = xi;
         a.g_len = ctx->lmax_max + 1;
         a.h_len = 2 * ctx->lmax_max + 1;
-        a.flush = p.flush > 0 ? p.flush : 8;
+        a.flush = p.flush > 0 ? p.flush : 1;
         prof_begin(ctx, s);
-        hipLaunchKernelGGL(batched_mfma_f32_kernel<TM>, dim3((unsigned)total), dim3(kBThreads), 0, s, a);
+        if (bf16)
+            hipLaunchKernelGGL(batched_mfma_bf16x3_kernel<TM>, dim3((unsigned)total), dim3(kBThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(batched_mfma_f32_kernel<TM>, dim3((unsigned)total), dim3(kBThreads), 0, s, a);
         prof_end(ctx, s, 1);
         return hipGetLastError();
     };
@@ -446,31 +652,22 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
             e = contract(std::integral_constant<int, 2>());
         if (e != hipSuccess) return e;
     }
-    // fill
+    // fill: one job per mask
     {
-        BFillArgs f;
-        f.n_groups = p.n_groups;
-        f.xi = xi;
-        f.n_out = n_out;
-        for (int i = 0; i < 4; ++i) f.src[i] = i < n_out ? spec_src[i] : 0;
-        long long base = 0;
-        for (int gi = 0; gi < p.n_groups; ++gi) {
-            f.L[gi] = p.L[gi];
-            f.xi_off[gi] = xi_off[gi];
-            f.n_masks[gi] = p.n_masks[gi];
-            f.n_tiles[gi] = (p.L[gi] + kT) / kT;
-            f.pair_base[gi] = base;
-            base += (long long)f.n_tiles[gi] * (f.n_tiles[gi] + 1) / 2 * kGroup;
-            for (int m = 0; m < kGroup; ++m) {
-                f.lmax[gi][m] = m < p.n_masks[gi] ? p.lmax[gi][m] : -1;
-                f.out[gi][m] = m < p.n_masks[gi] ? p.out[gi][m] : nullptr;
+        FillJob jobs[kMaxFillJobs];
+        int n_jobs = 0;
+        for (int gi = 0; gi < p.n_groups; ++gi)
+            for (int m = 0; m < p.n_masks[gi]; ++m) {
+                FillJob& j = jobs[n_jobs++];
+                j.xi = xi + xi_off[gi][m];
+                j.out = p.out[gi][m];
+                j.lmax = p.lmax[gi][m];
+                j.dmax = p.lmax[gi][m];
+                j.block0 = 0;
             }
-        }
-        for (int gi = p.n_groups; gi < kMaxGroups; ++gi) f.pair_base[gi] = base;
         prof_begin(ctx, s);
-        hipLaunchKernelGGL(batched_fill_kernel, dim3((unsigned)base), dim3(256), 0, s, f);
+        hipError_t e = launch_fill_jobs(jobs, n_jobs, spec_src, n_out, s);
         prof_end(ctx, s, 2);
-        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

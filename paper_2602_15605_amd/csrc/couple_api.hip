@@ -110,7 +110,9 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
         return fail(ctx, COUPLE_EINVAL, "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB",
                     spectra);
     if (precision != COUPLE_FP64 && precision != COUPLE_FP32C)
-        return fail(ctx, COUPLE_EINVAL, "unknown precision %d", precision);
+        return fail(ctx, COUPLE_EINVAL,
+                    "precision %d: COUPLE_FP64 or COUPLE_FP32C here (the matrix-core forms are batched only)",
+                    precision);
     if ((spectra & COUPLE_TT) && !W_TT) return fail(ctx, COUPLE_EINVAL, "TT requested but W_TT is NULL");
     if ((spectra & COUPLE_TE) && !W_TP) return fail(ctx, COUPLE_EINVAL, "TE requested but W_TP is NULL");
     if ((spectra & (COUPLE_EE | COUPLE_BB)) && !W_PP)
@@ -452,7 +454,7 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
                need_pp = spectra & (COUPLE_EE | COUPLE_BB);
     if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
         return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
-    const bool mfma = precision == COUPLE_MFMA_FP32;
+    const bool mfma = precision == COUPLE_MFMA_FP32 || precision == COUPLE_MFMA_BF16X3;
     for (int m = 0; m < n_masks; ++m) {
         rc = check_common(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
                           need_pp ? W_PP[m] : nullptr, lmax_i[m], spectra, mfma ? COUPLE_FP64 : precision,
@@ -490,8 +492,9 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
             p.w[gi][2][m] = need_pp ? W_PP[src] : nullptr;
             p.out[gi][m] = out[src];
         }
-    p.flush = ctx->batched_flush;
-    p.tm = ctx->batched_tm;
+    const int ti = precision == COUPLE_MFMA_BF16X3 ? 1 : 0;
+    p.flush = ctx->batched_flush[ti];
+    p.tm = ctx->batched_tm[ti];
     int src4[4];
     const int n_out = output_sources(spectra, src4);
     hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, s);
@@ -499,49 +502,77 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
     return COUPLE_OK;
 }
 
-int couple_set_batched_tiles(couple_ctx* ctx, int row_tiles, int flush) {
+namespace {
+int tile_index(couple_ctx* ctx, int precision, int* ti) {
+    if (precision == COUPLE_MFMA_FP32) {
+        *ti = 0;
+        return COUPLE_OK;
+    }
+    if (precision == COUPLE_MFMA_BF16X3) {
+        *ti = 1;
+        return COUPLE_OK;
+    }
+    return fail(ctx, COUPLE_EINVAL, "precision=%d has no batched tile shape (COUPLE_MFMA_FP32 or COUPLE_MFMA_BF16X3)",
+                precision);
+}
+}  // namespace
+
+int couple_set_batched_tiles(couple_ctx* ctx, int precision, int row_tiles, int flush) {
     if (!ctx) return COUPLE_EINVAL;
     ctx->err.clear();
+    int ti;
+    int rc = tile_index(ctx, precision, &ti);
+    if (rc) return rc;
     if (row_tiles != 1 && row_tiles != 2 && row_tiles != 4)
         return fail(ctx, COUPLE_EINVAL, "row_tiles=%d: must be 1, 2 or 4", row_tiles);
     if (flush < 1 || flush > 16) return fail(ctx, COUPLE_EINVAL, "flush=%d outside [1, 16]", flush);
-    ctx->batched_tm = row_tiles;
-    ctx->batched_flush = flush;
+    ctx->batched_tm[ti] = row_tiles;
+    ctx->batched_flush[ti] = flush;
     return COUPLE_OK;
 }
 
-int couple_get_batched_tiles(const couple_ctx* ctx, int* row_tiles, int* flush) {
-    if (!ctx) return COUPLE_EINVAL;
-    if (row_tiles) *row_tiles = ctx->batched_tm;
-    if (flush) *flush = ctx->batched_flush;
-    return COUPLE_OK;
-}
-
-int couple_autotune_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const double* const* W_TT,
-                            const double* const* W_TP, const double* const* W_PP, const int* w_len_i,
-                            unsigned spectra, double* const* out, void* stream, int* best_row_tiles,
-                            int* best_flush, float* best_ms) {
+int couple_get_batched_tiles(couple_ctx* ctx, int precision, int* row_tiles, int* flush) {
     if (!ctx) return COUPLE_EINVAL;
     ctx->err.clear();
+    int ti;
+    int rc = tile_index(ctx, precision, &ti);
+    if (rc) return rc;
+    if (row_tiles) *row_tiles = ctx->batched_tm[ti];
+    if (flush) *flush = ctx->batched_flush[ti];
+    return COUPLE_OK;
+}
+
+int couple_autotune_batched(couple_ctx* ctx, int precision, int n_masks, const int* lmax_i,
+                            const double* const* W_TT, const double* const* W_TP, const double* const* W_PP,
+                            const int* w_len_i, unsigned spectra, double* const* out, void* stream,
+                            int* best_row_tiles, int* best_flush, float* best_ms) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    int ti;
+    int rc = tile_index(ctx, precision, &ti);
+    if (rc) return rc;
     static const int kTm[] = {1, 2, 4};
-    static const int kFlush[] = {4, 8};
+    // flush candidates: float32 steps are 4 k, BF16x3 steps 32 k
+    static const int kFlush[2][2] = {{4, 8}, {1, 2}};
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
         return fail(ctx, COUPLE_EDEVICE, "event creation failed");
-    const int tm0 = ctx->batched_tm, fl0 = ctx->batched_flush;
+    }
+    const int tm0 = ctx->batched_tm[ti], fl0 = ctx->batched_flush[ti];
     float best = 3.4e38f;
-    int btm = tm0, bfl = fl0, rc = COUPLE_OK;
+    int btm = tm0, bfl = fl0;
     for (int tm : kTm)
-        for (int fl : kFlush) {
-            ctx->batched_tm = tm;
-            ctx->batched_flush = fl;
-            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, COUPLE_MFMA_FP32,
-                                       out, stream);  // warm-up (and argument check)
+        for (int fl : kFlush[ti]) {
+            ctx->batched_tm[ti] = tm;
+            ctx->batched_flush[ti] = fl;
+            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
+                                       stream);  // warm-up (and argument check)
             if (rc) break;
             (void)hipEventRecord(e0, s);
-            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, COUPLE_MFMA_FP32,
-                                       out, stream);
+            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
+                                       stream);
             (void)hipEventRecord(e1, s);
             if (rc) break;
             float ms = 0.0f;
@@ -560,12 +591,12 @@ int couple_autotune_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, con
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {
-        ctx->batched_tm = tm0;
-        ctx->batched_flush = fl0;
+        ctx->batched_tm[ti] = tm0;
+        ctx->batched_flush[ti] = fl0;
         return rc;
     }
-    ctx->batched_tm = btm;
-    ctx->batched_flush = bfl;
+    ctx->batched_tm[ti] = btm;
+    ctx->batched_flush[ti] = bfl;
     if (best_row_tiles) *best_row_tiles = btm;
     if (best_flush) *best_flush = bfl;
     if (best_ms) *best_ms = best;

@@ -68,8 +68,9 @@ struct couple_ctx {
     int* edges_host = nullptr;   // pinned staging for the bin edges
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
-    int batched_flush = 8;       // MFMA steps per Kahan flush of the batched kernel
-    int batched_tm = 2;          // row tiles per wavefront of the batched kernel
+    // tile shape of the batched matrix-core kernels, [0] float32, [1] BF16x3
+    int batched_flush[2] = {8, 2};   // MFMA steps per Kahan flush
+    int batched_tm[2] = {2, 2};      // 16-row tiles per wavefront
     std::string err;
     // measurement hook: event pairs recorded around each kernel
     bool profiling = false;
@@ -101,6 +102,18 @@ hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spe
                        double* out, hipStream_t s);
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                       const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
+// One fill job: Xi store [3][tri(lmax)] (Xi for diagonals d <= dmax, 0 beyond)
+// and its n_out output matrices [n_out][lmax+1][lmax+1].  block0 is set by
+// launch_fill_jobs.
+constexpr int kMaxFillJobs = kMaxGroups * kMaskGroup;
+struct FillJob {
+    const double* xi;
+    double* out;
+    int lmax;
+    int dmax;
+    int block0;
+};
+hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, hipStream_t s);
 // out[0 .. n) = 0 with a kernel (safe inside captured graphs)
 hipError_t launch_zero(double* out, size_t n, hipStream_t s);
 

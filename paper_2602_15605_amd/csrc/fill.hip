@@ -5,7 +5,8 @@
 // the upper one (Sec. 4.1); here that is done on Xi, and each 64 x 64 tile
 // of K is written with its own column factor.
 //
-// fill: one work-group per upper tile pair (I <= J).  The tile of Xi is read
+// fill: one work-group per upper tile pair (I <= J) of one job (a Xi store
+// and its output matrices; the batched form fills every mask in one launch).  The tile of Xi is read
 // diagonal by diagonal (consecutive l1 are consecutive in memory), kept in
 // LDS, and written twice: K[l1][l2] row by row and the mirrored tile
 // K[l2][l1] = (2 l1 + 1) Xi(l1, l2), also row by row, so both halves are
@@ -22,13 +23,8 @@ constexpr int kT = 64;           // tile edge
 constexpr int kFillThreads = 256;
 
 struct FillArgs {
-    const double* xi;
-    long long xi_stride;
-    double* out;
-    long long out_stride;        // (lmax+1)^2
-    int lmax;
-    int dmax;                    // Xi exists for d <= dmax, 0 beyond
-    int n_tiles;                 // tiles per edge
+    FillJob job[kMaxFillJobs];
+    int n_jobs;
     int n_out;
     int src[4];                  // Xi index of each output
 };
@@ -37,7 +33,6 @@ __device__ inline void pair_from_index(int t, int n, int* I, int* J) {
     // t enumerates (I, J), I <= J, row by row: row I holds n - I pairs
     int i = 0;
     int rem = t;
-    // closed form first guess, then correct
     while (rem >= n - i) {
         rem -= n - i;
         ++i;
@@ -49,17 +44,24 @@ __device__ inline void pair_from_index(int t, int n, int* I, int* J) {
 __global__ void __launch_bounds__(kFillThreads)
 fill_kernel(FillArgs a) {
     __shared__ double tile[kT][kT + 1];
+    // job of this block: blocks [block0, block0 + n_tiles (n_tiles + 1) / 2) of each job
+    int jb = 0;
+    while (jb + 1 < a.n_jobs && (int)blockIdx.x >= a.job[jb + 1].block0) ++jb;
+    const FillJob& job = a.job[jb];
+    const int lmax = job.lmax;
     int I, J;
-    pair_from_index(blockIdx.x, a.n_tiles, &I, &J);
+    pair_from_index((int)blockIdx.x - job.block0, (lmax + kT) / kT, &I, &J);
     const int r0 = kT * I, c0 = kT * J;
     const int t = threadIdx.x;
+    const long long ld = lmax + 1;
+    const long long xi_stride = tri_size(lmax);
     int last_src = -1;
 
     for (int o = 0; o < a.n_out; ++o) {
         const int src = a.src[o];
         if (src != last_src) {
             __syncthreads();
-            const double* xi = a.xi + (long long)src * a.xi_stride;
+            const double* xi = job.xi + (long long)src * xi_stride;
             // diagonals d = dj + dl - 63, dl = 0 .. 126; element (r, c = r + dl - 63)
             for (int idx = t; idx < (2 * kT - 1) * kT; idx += kFillThreads) {
                 const int r = idx % kT;
@@ -67,20 +69,19 @@ fill_kernel(FillArgs a) {
                 const int c = r + dl - (kT - 1);
                 if (c < 0 || c >= kT) continue;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 > a.lmax || l2 > a.lmax || l2 < l1) continue;
+                if (l1 > lmax || l2 > lmax || l2 < l1) continue;
                 const int d = l2 - l1;
-                tile[r][c] = (d <= a.dmax) ? xi[diag_offset(a.lmax, d) + l1] : 0.0;
+                tile[r][c] = (d <= job.dmax) ? xi[diag_offset(lmax, d) + l1] : 0.0;
             }
             __syncthreads();
             last_src = src;
         }
-        double* out = a.out + (long long)o * a.out_stride;
-        const long long ld = a.lmax + 1;
+        double* out = job.out + (long long)o * ld * ld;
         if (I == J) {
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int r = idx / kT, c = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 > a.lmax || l2 > a.lmax) continue;
+                if (l1 > lmax || l2 > lmax) continue;
                 const double x = (c >= r) ? tile[r][c] : tile[c][r];
                 out[l1 * ld + l2] = (2.0 * l2 + 1.0) * x;
             }
@@ -88,12 +89,12 @@ fill_kernel(FillArgs a) {
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int r = idx / kT, c = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= a.lmax && l2 <= a.lmax) out[l1 * ld + l2] = (2.0 * l2 + 1.0) * tile[r][c];
+                if (l1 <= lmax && l2 <= lmax) out[l1 * ld + l2] = (2.0 * l2 + 1.0) * tile[r][c];
             }
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int c = idx / kT, r = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= a.lmax && l2 <= a.lmax) out[l2 * ld + l1] = (2.0 * l1 + 1.0) * tile[r][c];
+                if (l1 <= lmax && l2 <= lmax) out[l2 * ld + l1] = (2.0 * l1 + 1.0) * tile[r][c];
             }
         }
     }
@@ -159,21 +160,32 @@ hipError_t launch_zero(double* out, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                       double* out, hipStream_t s) {
+hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, hipStream_t s) {
+    if (n_jobs < 1 || n_jobs > kMaxFillJobs) return hipErrorInvalidValue;
     FillArgs a;
-    a.xi = ctx->xi;
-    a.xi_stride = tri_size(lmax);
-    a.out = out;
-    a.out_stride = (long long)(lmax + 1) * (lmax + 1);
-    a.lmax = lmax;
-    a.dmax = dmax;
-    a.n_tiles = (lmax + kT) / kT;
+    long long blocks = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        a.job[j] = jobs[j];
+        a.job[j].block0 = (int)blocks;
+        const long long nt = (jobs[j].lmax + kT) / kT;
+        blocks += nt * (nt + 1) / 2;
+    }
+    a.n_jobs = n_jobs;
     a.n_out = n_out;
     for (int i = 0; i < 4; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
-    const long long n_pairs = (long long)a.n_tiles * (a.n_tiles + 1) / 2;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)n_pairs), dim3(kFillThreads), 0, s, a);
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kFillThreads), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
+                       double* out, hipStream_t s) {
+    FillJob j;
+    j.xi = ctx->xi;
+    j.out = out;
+    j.lmax = lmax;
+    j.dmax = dmax;
+    j.block0 = 0;
+    return launch_fill_jobs(&j, 1, spec_src, n_out, s);
 }
 
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,

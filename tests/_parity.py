@@ -11,6 +11,14 @@ import numpy as np
 
 TOL_FP64 = 1e-12
 TOL_FP32C = 1e-6
+# BF16x3 matrix-core form: each operand is split into bfloat16 hi + lo
+# (8 significant bits each, round to nearest), so |x - hi - lo| <= 2^-16 |x|;
+# the three kept products hi*hi + hi*lo + lo*hi miss lo*lo and the two split
+# residues, each at most 2^-16 of the product: 3 * 2^-16 = 4.58e-5 per term,
+# which bounds the sum's error relative to A_ref (the sum of |terms|).  On top
+# of it the float32 generation and accumulation, budgeted at 1e-6 as for the
+# float32 forms.
+TOL_BF16X3 = 3 * 2.0 ** -16 + 1e-6
 
 
 def parity_error(K, K_ref, A_ref):

@@ -1,5 +1,6 @@
 """Batched form: many masks of uneven lmax in one call, contracted on the
-matrix cores (COUPLE_MFMA_FP32), checked per mask against the oracle.
+matrix cores (COUPLE_MFMA_FP32 and COUPLE_MFMA_BF16X3), checked per mask
+against the oracle.
 
 The workload is 32 synthetic masks with lmax uniform in [500, 4000]; every
 mask is compared on >= 1% of its rows (at least 5, plus rows 0, 1, 2, lmax).
@@ -11,12 +12,12 @@ import sys
 import numpy as np
 import pytest
 
-from _parity import TOL_FP32C, assert_parity
+from _parity import TOL_BF16X3, TOL_FP32C, assert_parity
 
 pytestmark = pytest.mark.gpu
 
 SPEC4 = ("TT", "TE", "EE", "BB")
-TOL_MFMA = TOL_FP32C
+MFMA = [("mfma_fp32", TOL_FP32C), ("mfma_bf16x3", TOL_BF16X3)]
 
 
 def _say(*a):
@@ -45,33 +46,37 @@ def _rand_windows(lmaxes, seed):
     return [[rng.uniform(0.05, 1.5, 2 * L + 1) for _ in range(3)] for L in lmaxes]
 
 
-def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk):
+@pytest.mark.parametrize("precision,tol", MFMA)
+def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk, precision, tol):
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     lmaxes = [257, 3, 64, 0, 65, 200, 1, 130, 17, 2, 255, 100, 31, 32, 33, 150, 90]   # 17 masks: 2 groups
+    _say("batched small full parity %s, lmax %s" % (precision, lmaxes))
     Ws = _rand_windows(lmaxes, 5)
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
-    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision="mfma_fp32")
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
     torch.cuda.synchronize()
     worst = 0.0
     for m, L in enumerate(lmaxes):
         K = outs[m].cpu().numpy()
         Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], spectra=SPEC4)
         for i, s in enumerate(SPEC4):
-            worst = max(worst, assert_parity(K[i], Kr[i], Ar[i], TOL_MFMA, "mask %d lmax %d %s" % (m, L, s)))
+            worst = max(worst, assert_parity(K[i], Kr[i], Ar[i], tol, "mask %d lmax %d %s" % (m, L, s)))
         assert np.array_equal(K[2], K[3])
-    _say("batched small: max rel err %.3e" % worst)
+    _say("batched small %s: max rel err %.3e" % (precision, worst))
 
 
-def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk):
+@pytest.mark.parametrize("precision,tol", MFMA)
+def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, tol):
     from paper_2602_15605_amd import couple, synth
     torch = torch_gpu
     lmaxes = [int(x) for x in synth.batched_lmaxes()]
+    _say("workload3 batched %s" % precision)
     Ws = [synth.workload_windows(3, mask=m) for m in range(len(lmaxes))]
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
-    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision="mfma_fp32")
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
     torch.cuda.synchronize()
     worst = {s: 0.0 for s in SPEC4}
     for m, L in enumerate(lmaxes):
@@ -79,8 +84,8 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk):
         got = outs[m][:, torch.as_tensor(rows.astype(np.int64)).cuda(), :].cpu().numpy()
         Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], rows=rows, spectra=SPEC4)
         for i, s in enumerate(SPEC4):
-            worst[s] = max(worst[s], assert_parity(got[i], Kr[i], Ar[i], TOL_MFMA, "mask %d lmax %d %s" % (m, L, s)))
-    _say("workload3 batched mfma_fp32 max rel err: " + ", ".join("%s %.3e" % kv for kv in worst.items()))
+            worst[s] = max(worst[s], assert_parity(got[i], Kr[i], Ar[i], tol, "mask %d lmax %d %s" % (m, L, s)))
+    _say("workload3 batched %s max rel err: " % precision + ", ".join("%s %.3e" % kv for kv in worst.items()))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
@@ -109,13 +114,20 @@ def test_batched_errors(torch_gpu, ctx):
         couple.couple_reserve_batched(ctx, list(range(65)))
     fresh = couple.couple_init(100)
     try:
-        with pytest.raises(couple.CoupleError, match="couple_reserve_batched"):
-            couple.couple_matrix_batched(fresh, [40], w, None, None, spectra=("TT",), precision="mfma_fp32")
+        for prec in ("mfma_fp32", "mfma_bf16x3"):
+            with pytest.raises(couple.CoupleError, match="couple_reserve_batched"):
+                couple.couple_matrix_batched(fresh, [40], w, None, None, spectra=("TT",), precision=prec)
     finally:
         couple.couple_free(fresh)
+    with pytest.raises(couple.CoupleError, match="batched tile shape"):
+        couple.couple_set_batched_tiles(ctx, 2, 8, precision="fp32c")
+    with pytest.raises(couple.CoupleError, match="batched only"):
+        couple.couple_matrix(ctx, w[0], None, None, 40, spectra=("TT",), precision="mfma_bf16x3")
 
 
-def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk):
+@pytest.mark.parametrize("precision,tol,flushes", [("mfma_fp32", TOL_FP32C, (1, 4, 8, 16)),
+                                                    ("mfma_bf16x3", TOL_BF16X3, (1, 2, 4))])
+def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk, precision, tol, flushes):
     """Every tile shape gives a result within the bar; the autotuner keeps one of them."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
@@ -124,27 +136,32 @@ def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk):
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
     refs = [oracle_bulk.coupling_rows(L, *Ws[m], spectra=SPEC4) for m, L in enumerate(lmaxes)]
-    saved = couple.couple_get_batched_tiles(ctx)
+    saved = couple.couple_get_batched_tiles(ctx, precision=precision)
+    other = "mfma_bf16x3" if precision == "mfma_fp32" else "mfma_fp32"
+    saved_other = couple.couple_get_batched_tiles(ctx, precision=other)
     try:
         for tm in (1, 2, 4):
-            for fl in (1, 4, 8, 16):
-                couple.couple_set_batched_tiles(ctx, tm, fl)
-                outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32")
+            for fl in flushes:
+                _say("%s row_tiles %d flush %d" % (precision, tm, fl))
+                couple.couple_set_batched_tiles(ctx, tm, fl, precision=precision)
+                outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision)
                 for m in range(len(lmaxes)):
                     K = outs[m].cpu().numpy()
                     for i, s in enumerate(SPEC4):
-                        assert_parity(K[i], refs[m][0][i], refs[m][1][i], TOL_MFMA, "tm %d flush %d %s" % (tm, fl, s))
-        tm, fl, ms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2])
-        assert tm in (1, 2, 4) and fl in (4, 8) and ms > 0
-        assert couple.couple_get_batched_tiles(ctx) == (tm, fl)
-        _say("autotune picked row_tiles=%d flush=%d (%.3f ms)" % (tm, fl, ms))
+                        assert_parity(K[i], refs[m][0][i], refs[m][1][i], tol, "tm %d flush %d %s" % (tm, fl, s))
+        tm, fl, ms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision)
+        assert tm in (1, 2, 4) and fl in flushes and ms > 0
+        assert couple.couple_get_batched_tiles(ctx, precision=precision) == (tm, fl)
+        assert couple.couple_get_batched_tiles(ctx, precision=other) == saved_other
+        _say("autotune %s picked row_tiles=%d flush=%d (%.3f ms)" % (precision, tm, fl, ms))
         with pytest.raises(couple.CoupleError):
-            couple.couple_set_batched_tiles(ctx, 3, 8)
+            couple.couple_set_batched_tiles(ctx, 3, 8, precision=precision)
     finally:
-        couple.couple_set_batched_tiles(ctx, *saved)
+        couple.couple_set_batched_tiles(ctx, *saved, precision=precision)
 
 
-def test_batched_graph_replay(torch_gpu, ctx):
+@pytest.mark.parametrize("precision", ["mfma_fp32", "mfma_bf16x3"])
+def test_batched_graph_replay(torch_gpu, ctx, precision):
     """The batched call is capture-safe: a captured graph replays to the eager result,
     replay after replay, with eager work in between."""
     from paper_2602_15605_amd import couple
@@ -154,16 +171,16 @@ def test_batched_graph_replay(torch_gpu, ctx):
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
     eager = [o.clone() for o in couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2],
-                                                            precision="mfma_fp32")]
+                                                            precision=precision)]
     outs = [torch.empty_like(o) for o in eager]
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32", outs=outs)
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision, outs=outs)
     torch.cuda.current_stream().wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision="mfma_fp32", outs=outs)
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision, outs=outs)
     for rep in range(4):
         for o in outs:
             o.fill_(float("nan"))
