@@ -50,8 +50,15 @@ enum couple_status {
     COUPLE_ENOTSUP = -4   /* valid request this build does not implement           */
 };
 
-/* spectra bit mask */
-enum couple_spectrum { COUPLE_TT = 1, COUPLE_TE = 2, COUPLE_EE = 4, COUPLE_BB = 8 };
+/* spectra bit mask; outputs are written in this order */
+enum couple_spectrum {
+    COUPLE_TT = 1,
+    COUPLE_TE = 2,
+    COUPLE_EE = 4,
+    COUPLE_BB = 8,
+    COUPLE_EB = 16  /* odd-L leakage kernel of App. A: S^EB = [(1-(-1)^L)/2]^2 (l1 l2 l3; -2 2 0)^2
+                       with W_PP (the E-B mixing block of the MASTER polarization matrix) */
+};
 
 /* arithmetic of the l3 reduction */
 enum couple_precision {
@@ -97,10 +104,12 @@ const char *couple_last_error(const couple_ctx *ctx);
  * couple_matrix -- full coupling matrices (Sec. 2 eqs. K_TT, K_EE; App. A).
  *   W_TT, W_TP, W_PP : device float64 window spectra W_l, l = 0 .. w_len-1.
  *                      Only those the requested spectra use must be non-NULL
- *                      (TT -> W_TT, TE -> W_TP, EE/BB -> W_PP).
+ *                      (TT -> W_TT, TE -> W_TP, EE/BB/EB -> W_PP).
  *   w_len            : >= 2*lmax + 1 (W_L is needed for L <= 2 lmax, Sec. 4).
  *   lmax             : 0 <= lmax <= lmax_max of ctx.
- *   spectra          : non-empty OR of COUPLE_TT/TE/EE/BB.
+ *   spectra          : non-empty OR of COUPLE_TT/TE/EE/BB/EB; output i is the
+ *                      i-th requested spectrum in the order TT, TE, EE, BB, EB.
+ *                      EB (odd L) is a second pass over the triangle.
  *   precision        : COUPLE_FP64 or COUPLE_FP32C.
  *   out              : device float64, popcount(spectra) * (lmax+1)^2 entries,
  *                      8-byte aligned; fully overwritten.
@@ -170,7 +179,7 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *   out             : HOST array of n_masks DEVICE float64 pointers; mask m
  *                     gets popcount(spectra) (lmax_i[m]+1)^2 entries in the
  *                     couple_matrix layout.
- *   precision       : COUPLE_MFMA_FP32 or COUPLE_MFMA_BF16X3 -- one
+ *   precision       : COUPLE_MFMA_FP32 or COUPLE_MFMA_BF16X3 (no EB: ENOTSUP) -- one
  *                     contraction launch for the whole batch (plus a window
  *                     table kernel before and one fill kernel after): masks
  *                     sorted by lmax in groups of 16 share every generated

@@ -18,9 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcouple.so")
 
 COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EDEVICE, COUPLE_ENOTSUP = 0, -1, -2, -3, -4
-TT, TE, EE, BB = 1, 2, 4, 8
-SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB}
-SPECTRUM_ORDER = ("TT", "TE", "EE", "BB")
+TT, TE, EE, BB, EB = 1, 2, 4, 8, 16
+SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB, "EB": EB}
+SPECTRUM_ORDER = ("TT", "TE", "EE", "BB", "EB")
 PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2, "mfma_bf16x3": 3}
 LMAX_LIMIT = 16384
 
@@ -127,7 +127,7 @@ def _spectra_bits(spectra) -> int:
 
 
 def _n_spec(bits: int) -> int:
-    return bin(bits & 0xF).count("1")
+    return bin(bits & 0x1F).count("1")
 
 
 def _dev_ptr(t, name):

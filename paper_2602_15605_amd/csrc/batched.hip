@@ -334,13 +334,15 @@ batched_mfma_f32_kernel(BatchArgs a) {
 // k < 0 and k > kmax contribute 0 through S(k) = 0.
 
 // v -> (hi, lo) bfloat16 with hi = RN(v), lo = RN(v - hi): 8 values, packed
-// two at a time by v_cvt_pk_bf16_f32; float(hi) is read back from the bits.
+// two at a time by v_cvt_pk_bf16_f32; float(hi) is read back from the packed
+// bits (a byte permute moves the low half up, a mask keeps the high half).
 __device__ inline void split_bf16(const float (&v)[8], bf8v& hi, bf8v& lo) {
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
         const bf2v h = {(__bf16)v[e], (__bf16)v[e + 1]};
         const unsigned hb = __builtin_bit_cast(unsigned, h);
-        const float f0 = __builtin_bit_cast(float, hb << 16);
+        // bytes [hb.1, hb.0, 0, 0]: selector 1 / 0 pick bytes of the second operand, 0x0c gives 0
+        const float f0 = __builtin_bit_cast(float, __builtin_amdgcn_perm(0u, hb, 0x01000c0cu));
         const float f1 = __builtin_bit_cast(float, hb & 0xffff0000u);
         const bf2v l = {(__bf16)(v[e] - f0), (__bf16)(v[e + 1] - f1)};
         hi[e] = h[0];

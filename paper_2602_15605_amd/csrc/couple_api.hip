@@ -98,6 +98,7 @@ int output_sources(unsigned spectra, int* src) {
     if (spectra & COUPLE_TE) src[n++] = 1;
     if (spectra & COUPLE_EE) src[n++] = 2;
     if (spectra & COUPLE_BB) src[n++] = 2;
+    if (spectra & COUPLE_EB) src[n++] = 3;
     return n;
 }
 
@@ -106,8 +107,8 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
                  unsigned spectra, int precision, const double* out) {
     if (lmax < 0 || lmax > ctx->lmax_max)
         return fail(ctx, COUPLE_EINVAL, "lmax=%d outside [0, lmax_max=%d]", lmax, ctx->lmax_max);
-    if (spectra == 0 || (spectra & ~0xFu))
-        return fail(ctx, COUPLE_EINVAL, "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB",
+    if (spectra == 0 || (spectra & ~0x1Fu))
+        return fail(ctx, COUPLE_EINVAL, "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB|EB",
                     spectra);
     if (precision != COUPLE_FP64 && precision != COUPLE_FP32C)
         return fail(ctx, COUPLE_EINVAL,
@@ -115,8 +116,8 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
                     precision);
     if ((spectra & COUPLE_TT) && !W_TT) return fail(ctx, COUPLE_EINVAL, "TT requested but W_TT is NULL");
     if ((spectra & COUPLE_TE) && !W_TP) return fail(ctx, COUPLE_EINVAL, "TE requested but W_TP is NULL");
-    if ((spectra & (COUPLE_EE | COUPLE_BB)) && !W_PP)
-        return fail(ctx, COUPLE_EINVAL, "EE/BB requested but W_PP is NULL");
+    if ((spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB)) && !W_PP)
+        return fail(ctx, COUPLE_EINVAL, "EE/BB/EB requested but W_PP is NULL");
     if (!out) return fail(ctx, COUPLE_EINVAL, "out is NULL");
     if (reinterpret_cast<uintptr_t>(out) % alignof(double))
         return fail(ctx, COUPLE_EINVAL, "out is not 8-byte aligned");
@@ -126,6 +127,7 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
 int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const double* W_PP, int lmax,
                   unsigned spectra, int precision, int l3_lo, int l3_hi, hipStream_t s) {
     const bool pol = (spectra & (COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0;
+    const bool even = pol || (spectra & COUPLE_TT);
     // windows are needed for l3 <= min(l3_hi, 2 lmax)
     const int n = std::min(l3_hi, 2 * lmax) + 1;
     hipError_t e;
@@ -133,14 +135,20 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
         Timed t(ctx, s, 0);
         e = couple::launch_scale_windows(ctx, (spectra & COUPLE_TT) ? W_TT : nullptr,
                                          (spectra & COUPLE_TE) ? W_TP : nullptr,
-                                         (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n, s);
+                                         (spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB)) ? W_PP : nullptr, n, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
-    {
+    if (even) {
         Timed t(ctx, s, 1);
-        e = couple::launch_strip(ctx, lmax, pol, precision, l3_lo, std::min(l3_hi, 2 * lmax), s);
+        e = couple::launch_strip(ctx, lmax, pol ? couple::kStripPol : couple::kStripTT, precision, l3_lo,
+                                 std::min(l3_hi, 2 * lmax), s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "strip launch");
+    if (spectra & COUPLE_EB) {
+        Timed t(ctx, s, 1);
+        e = couple::launch_strip(ctx, lmax, couple::kStripEB, precision, l3_lo, std::min(l3_hi, 2 * lmax), s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "odd-L strip launch");
     return COUPLE_OK;
 }
 
@@ -196,7 +204,7 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
         {(void**)&c->g_pad, ng * sizeof(double)},   {(void**)&c->h_pad, nh * sizeof(double)},
         {(void**)&c->gf_pad, ng * sizeof(float)},   {(void**)&c->hf_pad, nh * sizeof(float)},
         {(void**)&c->cl, (lmax_max + 1) * sizeof(double)},
-        {(void**)&c->xi, 3 * (size_t)couple::tri_size(lmax_max) * sizeof(double)},
+        {(void**)&c->xi, 4 * (size_t)couple::tri_size(lmax_max) * sizeof(double)},
         {(void**)&c->wp, nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
         {(void**)&c->edges_dev, (lmax_max + 2) * sizeof(int)},
     };
@@ -246,7 +254,7 @@ int couple_matrix(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = run_reduction(ctx, W_TT, W_TP, W_PP, lmax, spectra, precision, 0, 2 * lmax, s);
     if (rc) return rc;
-    int src[4];
+    int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     hipError_t e;
     {
@@ -291,7 +299,7 @@ int upload_edges(couple_ctx* ctx, const int* bin_edges, int n_bins, hipStream_t 
 // One mask of a band-limited call, edges (if any) already on the device.
 int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP, const double* W_PP,
              int lmax, unsigned spectra, int precision, bool binned, int n_bins, double* out, hipStream_t s) {
-    int src[4];
+    int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     const int hi = std::min(l3_hi, 2 * lmax);
     const int dmax = std::min(lmax, hi);
@@ -362,7 +370,7 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
         rc = upload_edges(ctx, bin_edges, n_bins, s);
         if (rc) return rc;
     }
-    int src[4];
+    int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     const size_t per_mask = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
     for (int m = 0; m < n_masks; ++m) {
@@ -455,6 +463,8 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
     if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
         return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
     const bool mfma = precision == COUPLE_MFMA_FP32 || precision == COUPLE_MFMA_BF16X3;
+    if (mfma && (spectra & COUPLE_EB))
+        return fail(ctx, COUPLE_ENOTSUP, "EB is not in the matrix-core batched form (use COUPLE_FP64 or COUPLE_FP32C)");
     for (int m = 0; m < n_masks; ++m) {
         rc = check_common(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
                           need_pp ? W_PP[m] : nullptr, lmax_i[m], spectra, mfma ? COUPLE_FP64 : precision,
@@ -495,7 +505,7 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
     const int ti = precision == COUPLE_MFMA_BF16X3 ? 1 : 0;
     p.flush = ctx->batched_flush[ti];
     p.tm = ctx->batched_tm[ti];
-    int src4[4];
+    int src4[couple::kMaxOut];
     const int n_out = output_sources(spectra, src4);
     hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");

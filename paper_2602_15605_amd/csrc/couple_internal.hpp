@@ -61,7 +61,7 @@ struct couple_ctx {
     float* hf_pad = nullptr;
     double* cl = nullptr;        // c_l, l = 0 .. lmax_max
     // workspace
-    double* xi = nullptr;        // 3 packed upper triangles (TT, TE, EE)
+    double* xi = nullptr;        // 4 packed upper triangles (TT, TE, EE, EB)
     double* wp = nullptr;        // scaled windows (2l+1) W_l / (4 pi), 3 x (2 lmax_max + 1)
     float* wpf = nullptr;        // float32 copies
     int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
@@ -90,14 +90,17 @@ namespace couple {
 hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
 
 // strip kernels (strip.hip): Xi on the packed upper triangle.
-//   pol: also TE and EE.  l3 restricted to [l3_lo, l3_hi].
+//   mode kStripTT: Xi_TT; kStripPol: Xi_TT, Xi_TE, Xi_EE (even L);
+//   kStripEB: Xi_EB (odd L, fourth triangle).  l3 restricted to [l3_lo, l3_hi].
+enum { kStripTT = 0, kStripPol = 1, kStripEB = 2 };
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
                                 const double* wpp, int n, hipStream_t s);
-hipError_t launch_strip(const couple_ctx* ctx, int lmax, bool pol, int precision, int l3_lo,
+hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,
                         int l3_hi, hipStream_t s);
 
 // fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
-//   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE) output i comes from, n_out outputs.
+//   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE, 3 EB) output i comes from, n_out <= kMaxOut outputs.
+constexpr int kMaxOut = 5;
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                        double* out, hipStream_t s);
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,

@@ -10,7 +10,8 @@
 // diagonal by diagonal (consecutive l1 are consecutive in memory), kept in
 // LDS, and written twice: K[l1][l2] row by row and the mirrored tile
 // K[l2][l1] = (2 l1 + 1) Xi(l1, l2), also row by row, so both halves are
-// coalesced.  K^BB is written from the same LDS values as K^EE.
+// coalesced.  K^BB is written from the same LDS values as K^EE.  Xi_EB is
+// symmetric as well (the (-2 2 0)^2 of odd L is even under l1 <-> l2).
 //
 // bin: K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2} per
 // (b, b') work-group, reduced in a fixed order.
@@ -26,7 +27,7 @@ struct FillArgs {
     FillJob job[kMaxFillJobs];
     int n_jobs;
     int n_out;
-    int src[4];                  // Xi index of each output
+    int src[kMaxOut];            // Xi index of each output
 };
 
 __device__ inline void pair_from_index(int t, int n, int* I, int* J) {
@@ -111,7 +112,7 @@ struct BinArgs {
     int lmax;
     int dmax;
     int n_out;
-    int src[4];
+    int src[kMaxOut];
 };
 
 __global__ void __launch_bounds__(kBinThreads)
@@ -172,7 +173,7 @@ hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src
     }
     a.n_jobs = n_jobs;
     a.n_out = n_out;
-    for (int i = 0; i < 4; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
+    for (int i = 0; i < kMaxOut; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kFillThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -199,7 +200,7 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
     a.lmax = lmax;
     a.dmax = dmax;
     a.n_out = n_out;
-    for (int i = 0; i < 4; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
+    for (int i = 0; i < kMaxOut; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(n_bins * n_bins)), dim3(kBinThreads), 0, s, a);
     return hipGetLastError();
 }

@@ -37,6 +37,22 @@
 //
 // and s = 0 for l1 < 2 or l2 < 2, where the (-2 2 0) symbol vanishes.
 //
+// Odd L (the EB kernel of App. A, S^EB = (-2 2 0)^2 on odd L).  With
+// (j1, j2, j3) = (l3, l1, l2) and J = L odd, the (0 0 0) term of
+// eq. 022_rearranged vanishes, and both (0 -1 1) symbols reduce to the one
+// (0 0 0) symbol of even total Y' = (l1, l2+1, l3; 0 0 0): the unshifted one
+// by eq. joneodd, the shifted one (even total) by eq. joneevensimp with
+// j3 -> j3 + 1.  Collecting the factors,
+//
+//     (l1 l2 l3; -2 2 0)^2 = Y'^2 s^2 (sig(sig+1) - c)(c - d(d+1))(c + mu)^2,
+//     sig = l1 + l2 + 1,  tau = sig + 1,  mu = 2 (l1+2)(l2+2) - tau(tau+1),
+//
+// every factor an integer.  Y'^2 is the (0 0 0)^2 of the pair (l1, l2+1),
+// i.e. the TT term of diagonal d+1 with l3 = d + 1 + 2k, so the odd-L pass is
+// the same strip walk on diagonal d+1 with U_EB(k) = W'_PP(l3) g(k) g(d+1+k)
+// (c - d(d+1)) and the row factor (sig(sig+1) - c)(c + mu)^2; its last step
+// (l3 = l1 + l2 + 1) has sig(sig+1) - c = 0.
+//
 // Mapping.  One wavefront per work item (d, block of 64 R consecutive l1);
 // lane i owns l1 = A + R i + j, j < R, and walks k.  g(l1 - k) and
 // h(l1 + d + k) are kept in registers as windows of R values that slide by
@@ -93,9 +109,14 @@ struct Win {
     __device__ static inline int phys(int slot) { return slot + slot / R; }
 };
 
-template <int R, bool POL>
+// Kernel modes: TT only; TT + TE + EE (even L); EB (odd L).
+enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2 };
+
+template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
 strip_fp64_kernel(StripArgs a) {
+    constexpr bool POL = MODE == kModePol;
+    constexpr bool EB = MODE == kModeEB;
     using W = Win<R>;
     constexpr int B = W::kB;
     constexpr int KC = kStripChunk;
@@ -113,24 +134,32 @@ strip_fp64_kernel(StripArgs a) {
             item -= nb;
         }
     }
-    const int d = item;
+    const int d = item;                                  // l2 = l1 + d
+    const int de = EB ? d + 1 : d;                       // l3 = de + 2k
     const int A = B * b;
     const int n_valid = a.lmax - d + 1;                  // l1 = 0 .. n_valid - 1
     const int blk_max = min(A + B, n_valid) - 1;         // largest l1 in this block
-    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);     // ceil((l3_lo - d)/2)
-    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);   // floor((l3_hi - d)/2)
+    const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);    // ceil((l3_lo - de)/2)
+    const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);  // floor((l3_hi - de)/2)
 
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
 
+    // gam2, kap: N' = c (c - gam2) + kap (even L); for EB: sig(sig+1) and mu
     double tt[R], te[R], ee[R], gam2[R], kap[R], gw[R], hw[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         tt[j] = te[j] = ee[j] = 0.0;
         const long long l1 = l1_0 + j, l2 = l1 + d;
-        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
-        gam2[j] = (double)(2 * (aa + bb - 1));
-        kap[j] = (double)(aa * (aa - 2) + bb * (bb - 2));
+        if (EB) {
+            const long long sg = l1 + l2 + 1, tau = sg + 1;
+            gam2[j] = (double)(sg * (sg + 1));
+            kap[j] = (double)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
+        } else {
+            const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+            gam2[j] = (double)(2 * (aa + bb - 1));
+            kap[j] = (double)(aa * (aa - 2) + bb * (bb - 2));
+        }
     }
 
     const double* wtt = a.wp;
@@ -142,7 +171,7 @@ strip_fp64_kernel(StripArgs a) {
         __syncthreads();
         // stage g(e), e = A - k0 - KC + 1 + slot; h(e), e = A + d + k0 + slot
         const int g_base = A - k0 - KC + 1;
-        const int h_base = A + d + k0;
+        const int h_base = A + de + k0;
         for (int slot = lane; slot < W::kLen; slot += kWave) {
             const int eg = g_base + slot, eh = h_base + slot;
             s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
@@ -152,13 +181,19 @@ strip_fp64_kernel(StripArgs a) {
             double4 u = {0.0, 0.0, 0.0, 0.0};
             if (s < kc) {
                 const int k = k0 + s;
-                const int l3 = d + 2 * k;
-                const double gg = a.g[k] * a.g[d + k];
-                u.x = wtt[l3] * gg;
-                if (POL) {
-                    u.y = wtp[l3] * gg;
-                    u.z = wpp[l3] * gg;
-                    u.w = (double)((long long)l3 * (l3 + 1));
+                const int l3 = de + 2 * k;
+                const double gg = a.g[k] * a.g[de + k];
+                const long long c = (long long)l3 * (l3 + 1);
+                if (EB) {
+                    u.x = wpp[l3] * gg * (double)(c - (long long)d * (d + 1));
+                    u.w = (double)c;
+                } else {
+                    u.x = wtt[l3] * gg;
+                    if (POL) {
+                        u.y = wtp[l3] * gg;
+                        u.z = wpp[l3] * gg;
+                        u.w = (double)c;
+                    }
                 }
             }
             s_u[s] = u;
@@ -195,6 +230,13 @@ strip_fp64_kernel(StripArgs a) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const double P = gw[j] * hw[j];
+                    if (EB) {
+                        // (sig(sig+1) - c) (c + mu)^2, each factor an exact integer
+                        const double f1 = gam2[j] - uu.w;
+                        const double f3 = uu.w + kap[j];
+                        tt[j] = __builtin_fma(uu.x, P * ((f1 * f3) * f3), tt[j]);
+                        continue;
+                    }
                     tt[j] = __builtin_fma(uu.x, P, tt[j]);
                     if (POL) {
                         const double dc = uu.w - gam2[j];
@@ -215,6 +257,11 @@ strip_fp64_kernel(StripArgs a) {
     for (int j = 0; j < R; ++j) {
         const int l1 = l1_0 + j;
         if (l1 < n_valid) {
+            if (EB) {
+                const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
+                a.xi[3 * a.xi_stride + off + l1] = (s * s) * tt[j];
+                continue;
+            }
             a.xi[off + l1] = tt[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
@@ -245,9 +292,11 @@ strip_fp64_kernel(StripArgs a) {
 // the pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.
 constexpr int kCompBlock = 2 * kStripR;
 
-template <int R, bool POL>
+template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
 strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
+    constexpr bool POL = MODE == kModePol;
+    constexpr bool EB = MODE == kModeEB;
     using W = Win<R>;
     constexpr int B = W::kB;
     constexpr int KC = kStripChunk;
@@ -266,12 +315,13 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             item -= nb;
         }
     }
-    const int d = item;
+    const int d = item;                                  // l2 = l1 + d
+    const int de = EB ? d + 1 : d;                       // l3 = de + 2k
     const int A = B * b;
     const int n_valid = a.lmax - d + 1;
     const int blk_max = min(A + B, n_valid) - 1;
-    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
-    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+    const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);
 
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
@@ -279,14 +329,23 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     // Kahan pairs (sum, compensation) per spectrum and lane-owned l1
     float kt[R], kte[R], kee[R], ct[R], cte[R], cee[R];
     float gw[R], hw[R], beta[R];
-    int gam[R];
+    // even L: gam = a + b - 1, beta = 2ab + 1; EB: gam = sig(sig+1), mu
+    int gam[R], mu[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         kt[j] = kte[j] = kee[j] = ct[j] = cte[j] = cee[j] = 0.0f;
         const long long l1 = l1_0 + j, l2 = l1 + d;
-        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
-        gam[j] = (int)(aa + bb - 1);
-        beta[j] = (float)(2.0 * (double)aa * (double)bb + 1.0);
+        if (EB) {
+            const long long sg = l1 + l2 + 1, tau = sg + 1;
+            gam[j] = (int)(sg * (sg + 1));
+            mu[j] = (int)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
+            beta[j] = 0.0f;
+        } else {
+            const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+            gam[j] = (int)(aa + bb - 1);
+            mu[j] = 0;
+            beta[j] = (float)(2.0 * (double)aa * (double)bb + 1.0);
+        }
     }
 
     const double* wtt = a.wp;
@@ -297,7 +356,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
         const int kc = min(KC, k_hi - k0 + 1);
         __syncthreads();
         const int g_base = A - k0 - KC + 1;
-        const int h_base = A + d + k0;
+        const int h_base = A + de + k0;
         for (int slot = lane; slot < W::kLen; slot += kWave) {
             const int eg = g_base + slot, eh = h_base + slot;
             s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? gf[eg] : 0.0f;
@@ -307,14 +366,20 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             float4 u = {0.0f, 0.0f, 0.0f, 0.0f};
             if (s < kc) {
                 const int k = k0 + s;
-                const int l3 = d + 2 * k;
-                const double gg = a.g[k] * a.g[d + k];
-                u.x = (float)(wtt[l3] * gg);
-                if (POL) {
-                    const int l3c = d + 2 * k0;
-                    u.y = (float)(wtp[l3] * gg);
-                    u.z = (float)(wpp[l3] * gg);
+                const int l3 = de + 2 * k;
+                const int l3c = de + 2 * k0;
+                const double gg = a.g[k] * a.g[de + k];
+                if (EB) {
+                    const long long c = (long long)l3 * (l3 + 1);
+                    u.x = (float)(wpp[l3] * gg * (double)(c - (long long)d * (d + 1)));
                     u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
+                } else {
+                    u.x = (float)(wtt[l3] * gg);
+                    if (POL) {
+                        u.y = (float)(wtp[l3] * gg);
+                        u.z = (float)(wpp[l3] * gg);
+                        u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
+                    }
                 }
             }
             s_u[s] = u;
@@ -329,14 +394,20 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
-        // t = T + D(k) with T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly
-        float thi[R], tlo[R];
+        // even L: t = T + D(k) with T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly.
+        // EB: f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c(de + 2 k0), and
+        //     f3 = c + mu = T3 + D(k), T3 = c(de + 2 k0) + mu, both split the same way.
+        float thi[R], tlo[R], t3hi[R], t3lo[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int l3c = d + 2 * k0;
-            const int T = l3c * (l3c + 1) - gam[j];
+            const int l3c = de + 2 * k0;
+            const int cc = l3c * (l3c + 1);
+            const int T = EB ? gam[j] - cc : cc - gam[j];
             thi[j] = (float)T;
             tlo[j] = (float)(T - (int)thi[j]);
+            const int T3 = cc + mu[j];
+            t3hi[j] = (float)T3;
+            t3lo[j] = (float)(T3 - (int)t3hi[j]);
         }
         const int kc_r = (kc + G - 1) / G * G;
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
@@ -361,6 +432,12 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const float P = gw[j] * hw[j];
+                        if (EB) {
+                            const float f1 = thi[j] + (tlo[j] - uu.w);
+                            const float f3 = t3hi[j] + (uu.w + t3lo[j]);
+                            bt[j] = __builtin_fmaf(uu.x, P * ((f1 * f3) * f3), bt[j]);
+                            continue;
+                        }
                         bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
                         if (POL) {
                             const float t = thi[j] + (uu.w + tlo[j]);
@@ -401,6 +478,11 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     for (int j = 0; j < R; ++j) {
         const int l1 = l1_0 + j;
         if (l1 < n_valid) {
+            if (EB) {
+                const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
+                a.xi[3 * a.xi_stride + off + l1] = (s * s) * ((double)kt[j] - (double)ct[j]);
+                continue;
+            }
             a.xi[off + l1] = (double)kt[j] - (double)ct[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
@@ -432,7 +514,7 @@ static long long count_items(int lmax, int dmax, int B, int* bmax_out) {
     return total;
 }
 
-hipError_t launch_strip(const couple_ctx* ctx, int lmax, bool pol, int precision, int l3_lo, int l3_hi,
+hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo, int l3_hi,
                         hipStream_t s) {
     constexpr int R = kStripR;
     StripArgs a;
@@ -456,15 +538,19 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, bool pol, int precision
     if (precision == COUPLE_FP32C) {
         const float* gf = ctx->gf_pad + kTablePad;
         const float* hf = ctx->hf_pad + kTablePad;
-        if (pol)
-            hipLaunchKernelGGL((strip_fp32c_kernel<R, true>), grid, block, 0, s, a, gf, hf);
+        if (mode == kStripEB)
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeEB>), grid, block, 0, s, a, gf, hf);
+        else if (mode == kStripPol)
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModePol>), grid, block, 0, s, a, gf, hf);
         else
-            hipLaunchKernelGGL((strip_fp32c_kernel<R, false>), grid, block, 0, s, a, gf, hf);
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeTT>), grid, block, 0, s, a, gf, hf);
     } else {
-        if (pol)
-            hipLaunchKernelGGL((strip_fp64_kernel<R, true>), grid, block, 0, s, a);
+        if (mode == kStripEB)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEB>), grid, block, 0, s, a);
+        else if (mode == kStripPol)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((strip_fp64_kernel<R, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }

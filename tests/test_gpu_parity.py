@@ -249,7 +249,7 @@ def test_error_codes_with_context(torch_gpu, ctx):
         (lambda: lib.couple_matrix(h, p, p, p, 21, -1, 15, 0, o, s), -1, "lmax"),
         (lambda: lib.couple_matrix(h, p, p, p, 100000, 6001, 15, 0, o, s), -1, "lmax"),
         (lambda: lib.couple_matrix(h, p, p, p, 21, 10, 0, 0, o, s), -1, "spectra"),
-        (lambda: lib.couple_matrix(h, p, p, p, 21, 10, 16, 0, o, s), -1, "spectra"),
+        (lambda: lib.couple_matrix(h, p, p, p, 21, 10, 32, 0, o, s), -1, "spectra"),
         (lambda: lib.couple_matrix(h, p, p, p, 21, 10, 15, 7, o, s), -1, "precision"),
         (lambda: lib.couple_matrix(h, None, p, p, 21, 10, 15, 0, o, s), -1, "W_TT"),
         (lambda: lib.couple_matrix(h, p, None, p, 21, 10, 2, 0, o, s), -1, "W_TP"),
