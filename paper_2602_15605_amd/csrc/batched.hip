@@ -77,6 +77,14 @@ struct BatchArgs {
     int flush;                      // MFMA steps per Kahan flush
 };
 
+// Waves per SIMD the register allocation is held to (the largest that does
+// not spill; the attribute also lets the accumulators share the unified
+// register file instead of a separate AGPR allocation).
+template <int TM>
+constexpr int kF32Waves = TM <= 2 ? 4 : 2;
+template <int TM>
+constexpr int kBF16Waves = TM == 1 ? 3 : (TM == 2 ? 2 : 1);
+
 template <int TM, int KC>
 struct BWin {
     static constexpr int kRows = 16 * TM;
@@ -219,7 +227,7 @@ __device__ inline void flush_acc(f4v (&acc)[TM][3], float (&ks)[TM][3][4], float
 // W' table per group: [3][wt_len][16] float32, row l3, zero beyond 2 lmax_m
 // and in the tail rows.
 template <int TM>
-__global__ void __launch_bounds__(kBThreads)
+__global__ void __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(kF32Waves<TM>, 8)))
 batched_mfma_f32_kernel(BatchArgs a) {
     constexpr int KC = kChunkF32;
     using W = BWin<TM, KC>;
@@ -357,7 +365,7 @@ struct BTile {
 };
 
 template <int TM>
-__global__ void __launch_bounds__(kBThreads)
+__global__ void __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(kBF16Waves<TM>, 8)))
 batched_mfma_bf16x3_kernel(BatchArgs a) {
     constexpr int KC = kChunkBF16;  // a multiple of two steps of 32 k
     using W = BWin<TM, KC>;

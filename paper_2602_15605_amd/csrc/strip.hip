@@ -97,9 +97,38 @@ struct StripArgs {
     int g_len, h_len;    // valid lengths of g and h
     int lmax;
     int dmax;            // largest diagonal computed
-    int bmax;            // largest l1 block index
+    int band;            // dmax < lmax: items on a (block, diagonal) grid
     int l3_lo, l3_hi;
 };
+
+// Work item -> (d, A): the block of rows A .. A + B - 1 of diagonal d, aligned
+// to the diagonal's last row l1 = lmax - d, so that the one partial block of a
+// diagonal holds its shortest rows (lanes with l1 < 0 are idle).  Block j of
+// diagonal d starts at A = lmax - d + 1 - B (j + 1) and runs lmax + 1 - d - B j
+// steps.  Returns false for an item that has no block.
+//   Whole triangle: level m = j + floor(d / B) holds (m + 1) B items with
+//   B m (m + 1) / 2 before it; trips fall with m, so longest run first.
+//   Band (dmax < lmax): item = j (dmax + 1) + d; the band bounds every trip.
+template <int B>
+__device__ inline bool strip_item(const StripArgs& a, int item, int* d_out, int* A_out) {
+    int d, j;
+    if (a.band) {
+        j = item / (a.dmax + 1);
+        d = item - j * (a.dmax + 1);
+    } else {
+        int m = (int)((sqrtf(8.0f * (float)item / (float)B + 1.0f) - 1.0f) * 0.5f);
+        while (B * (m + 1) * (m + 2) / 2 <= item) ++m;
+        while (m > 0 && B * m * (m + 1) / 2 > item) --m;
+        const int rem = item - B * m * (m + 1) / 2;
+        j = rem / B;
+        d = B * (m - j) + (rem - B * j);
+    }
+    const int n_valid = a.lmax - d + 1;
+    if (d > a.dmax || n_valid <= B * j) return false;
+    *d_out = d;
+    *A_out = n_valid - B * (j + 1);
+    return true;
+}
 
 template <int R>
 struct Win {
@@ -124,21 +153,11 @@ strip_fp64_kernel(StripArgs a) {
     __shared__ double s_h[W::kPhys];
     __shared__ double4 s_u[KC];
 
-    // ---- work item: level b from bmax down, d ascending within a level ----
-    int item = blockIdx.x;
-    int b = a.bmax;
-    for (; b > 0; --b) {
-        const int nb = min(a.lmax - B * b, a.dmax) + 1;
-        if (nb > 0) {
-            if (item < nb) break;
-            item -= nb;
-        }
-    }
-    const int d = item;                                  // l2 = l1 + d
+    int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
+    if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
     const int de = EB ? d + 1 : d;                       // l3 = de + 2k
-    const int A = B * b;
     const int n_valid = a.lmax - d + 1;                  // l1 = 0 .. n_valid - 1
-    const int blk_max = min(A + B, n_valid) - 1;         // largest l1 in this block
+    const int blk_max = A + B - 1;                       // largest l1 in this block
     const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);    // ceil((l3_lo - de)/2)
     const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);  // floor((l3_hi - de)/2)
 
@@ -256,7 +275,7 @@ strip_fp64_kernel(StripArgs a) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int l1 = l1_0 + j;
-        if (l1 < n_valid) {
+        if (l1 >= 0 && l1 < n_valid) {
             if (EB) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
                 a.xi[3 * a.xi_stride + off + l1] = (s * s) * tt[j];
@@ -290,7 +309,7 @@ strip_fp64_kernel(StripArgs a) {
 // Accumulation: each lane sums kCompBlock consecutive terms with float32 FMA
 // and adds the block sum into a Kahan (sum, compensation) pair in float32;
 // the pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.
-constexpr int kCompBlock = 2 * kStripR;
+constexpr int kCompBlock = 4 * kStripR;
 
 template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
@@ -306,20 +325,11 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     __shared__ float s_h[W::kPhys];
     __shared__ float4 s_u[KC];
 
-    int item = blockIdx.x;
-    int b = a.bmax;
-    for (; b > 0; --b) {
-        const int nb = min(a.lmax - B * b, a.dmax) + 1;
-        if (nb > 0) {
-            if (item < nb) break;
-            item -= nb;
-        }
-    }
-    const int d = item;                                  // l2 = l1 + d
+    int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
+    if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
     const int de = EB ? d + 1 : d;                       // l3 = de + 2k
-    const int A = B * b;
     const int n_valid = a.lmax - d + 1;
-    const int blk_max = min(A + B, n_valid) - 1;
+    const int blk_max = A + B - 1;
     const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);
     const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);
 
@@ -477,7 +487,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int l1 = l1_0 + j;
-        if (l1 < n_valid) {
+        if (l1 >= 0 && l1 < n_valid) {
             if (EB) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
                 a.xi[3 * a.xi_stride + off + l1] = (s * s) * ((double)kt[j] - (double)ct[j]);
@@ -503,15 +513,14 @@ hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const 
     return hipGetLastError();
 }
 
-static long long count_items(int lmax, int dmax, int B, int* bmax_out) {
-    const int bmax = lmax / B;
-    long long total = 0;
-    for (int b = bmax; b >= 0; --b) {
-        const int nb = std::min(lmax - B * b, dmax) + 1;
-        if (nb > 0) total += nb;
+// Items of the strip grid (see strip_item).
+static long long count_items(int lmax, int dmax, int B, bool band) {
+    if (band) {
+        const long long J = (lmax + B) / B;
+        return J * (dmax + 1);
     }
-    *bmax_out = bmax;
-    return total;
+    const long long M = lmax / B;
+    return (long long)B * (M + 1) * (M + 2) / 2;
 }
 
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo, int l3_hi,
@@ -531,7 +540,8 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     a.dmax = std::min(lmax, l3_hi);
     a.l3_lo = l3_lo;
     a.l3_hi = l3_hi;
-    const long long n_items = count_items(lmax, a.dmax, kWave * R, &a.bmax);
+    a.band = a.dmax < lmax ? 1 : 0;
+    const long long n_items = count_items(lmax, a.dmax, kWave * R, a.band != 0);
     if (n_items <= 0) return hipSuccess;
     if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_items), block(kWave);
