@@ -10,7 +10,8 @@
 // diagonal by diagonal (consecutive l1 are consecutive in memory), kept in
 // LDS, and written twice: K[l1][l2] row by row and the mirrored tile
 // K[l2][l1] = (2 l1 + 1) Xi(l1, l2), also row by row, so both halves are
-// coalesced.  K^BB is written from the same LDS values as K^EE.  Xi_EB is
+// coalesced.  K is written once and never read back here, so the stores
+// are non-temporal.  K^BB is written from the same LDS values as K^EE.  Xi_EB is
 // symmetric as well (the (-2 2 0)^2 of odd L is even under l1 <-> l2).
 //
 // bin: K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2} per
@@ -21,7 +22,7 @@ namespace couple {
 namespace {
 
 constexpr int kT = 64;           // tile edge
-constexpr int kFillThreads = 256;
+constexpr int kFillThreads = 512;  // 8 waves per tile: more stores in flight per LDS tile
 
 struct FillArgs {
     FillJob job[kMaxFillJobs];
@@ -84,18 +85,18 @@ fill_kernel(FillArgs a) {
                 const int l1 = r0 + r, l2 = c0 + c;
                 if (l1 > lmax || l2 > lmax) continue;
                 const double x = (c >= r) ? tile[r][c] : tile[c][r];
-                out[l1 * ld + l2] = (2.0 * l2 + 1.0) * x;
+                __builtin_nontemporal_store((2.0 * l2 + 1.0) * x, &out[l1 * ld + l2]);
             }
         } else {
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int r = idx / kT, c = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= lmax && l2 <= lmax) out[l1 * ld + l2] = (2.0 * l2 + 1.0) * tile[r][c];
+                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((2.0 * l2 + 1.0) * tile[r][c], &out[l1 * ld + l2]);
             }
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int c = idx / kT, r = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= lmax && l2 <= lmax) out[l2 * ld + l1] = (2.0 * l1 + 1.0) * tile[r][c];
+                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((2.0 * l1 + 1.0) * tile[r][c], &out[l2 * ld + l1]);
             }
         }
     }
