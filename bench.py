@@ -31,6 +31,31 @@ FLOP_PER_TRIPLE_POL = 16  # TT 5 + TE/EE 11
 FLOP_PER_TRIPLE_TT = 5
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "strip_pol4_lmax6000_traffic.md")
+STRIP_SOURCES = [os.path.join(ROOT, "paper_2602_15605_amd", "csrc", f) for f in ("strip.hip", "couple_internal.hpp")]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a strip kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when it is missing or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for path in STRIP_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    value = digest = None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch %s =" % kernel):
+            value = int(line.split("=")[1])
+        if line.startswith("kernel_source_sha256"):
+            digest = line.split("=")[1].strip()
+    return value if digest == h.hexdigest() else None
+
+
 def triples(lmax: int) -> int:
     """Even-L triples with l1 <= l2: C(lmax + 3, 3)."""
     return math.comb(lmax + 3, 3)
@@ -153,7 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=("fp64", "fp32c", "both"))
     ap.add_argument("--lmax", type=int, default=6000)
-    ap.add_argument("--cpu-rows", type=int, default=60, help="oracle rows timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=400, help="oracle rows timed for cpu_baseline (0: skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the band-limited and batched workload timings reported beside the headline")
@@ -285,8 +310,11 @@ def main():
                    "lmax": lmax, "spectra": list(spectra), "precision": head,
                    "triples": T, "elements_per_step": n_el},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS[head], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS[head], "traffic": None,
-                     "kernel": "strip (l3 reduction)", "flop_per_triple": FLOP_PER_TRIPLE_POL},
+                     "frac": achieved / PEAK_VALU_TFLOPS[head],
+                     "traffic": measured_traffic("strip_%s_kernel" % head),
+                     "kernel": "strip_%s_kernel (l3 reduction)" % head, "flop_per_triple": FLOP_PER_TRIPLE_POL,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                     "profiles/strip_pol4_lmax6000_traffic.md)"},
         "cpu_baseline": cpu,
         "precisions": results,
         "other_workloads": extras,
