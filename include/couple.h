@@ -134,6 +134,10 @@ int couple_matrix(couple_ctx *ctx, const double *W_TT, const double *W_TP, const
  *                  K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2}
  *                  (uniform average over the row bin, sum over the column bin).
  *   other arguments as couple_matrix (w_len >= min(l3_hi, 2 lmax) + 1).
+ * Asynchronous on stream, no allocation.  With n_bins <= 512 the bin edges
+ * travel in the kernel arguments, so the call only enqueues kernels (it can
+ * be captured in a graph); longer bin lists are staged through the
+ * context's pinned buffer after a synchronisation of stream.
  * Errors: as couple_matrix, plus EINVAL for a bad band or bin list.
  */
 int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const double *W_TP,
@@ -164,7 +168,7 @@ int couple_band_batched(couple_ctx *ctx, int n_masks, int l3_lo, int l3_hi, cons
  * workspace grows.  Size: 3 (lmax_m+1)(lmax_m+2)/2 float64 per mask (its Xi),
  * plus, per group of 16 masks sorted by lmax (L = the group's largest), the
  * larger of the two W' tables: 3 (2L+33) x 16 float32 or
- * 3 x 2 x 2 x 16 x (L+96 rounded up to 8) bfloat16.
+ * 3 x 2 x 2 x 16 x (L+64 rounded up to 8) bfloat16.
  * Errors: EINVAL (NULL ctx/lmax_i, n_masks outside [1, 64], lmax > lmax_max),
  * ENOMEM.
  */
@@ -198,12 +202,12 @@ int couple_matrix_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const
  * Tile shape of a batched matrix-core kernel (precision COUPLE_MFMA_FP32 or
  * COUPLE_MFMA_BF16X3, each keeps its own): row_tiles 16-row tiles of one
  * diagonal per wavefront (1, 2 or 4) and the number of MFMA steps between
- * Kahan flushes of the float32 matrix-core accumulators (1..16; a float32
- * step covers 4 l3 values, a BF16x3 step 32).  Defaults: float32 (2, 8),
- * BF16x3 (2, 2).
+ * flushes of the float32 matrix-core accumulators into the running sums
+ * (1..16; a float32 step covers 4 l3 values, a BF16x3 step 32).  Defaults:
+ * float32 (2, 8), BF16x3 (2, 4).
  *
  * couple_autotune_batched times every row_tiles in {1,2,4} with flush in
- * {4,8} (float32) or {1,2} (BF16x3) on the given batch (same arguments as
+ * {4,8} (float32) or {2,4} (BF16x3) on the given batch (same arguments as
  * couple_matrix_batched; out is overwritten), keeps the fastest in ctx for
  * later batched calls of that precision and returns it through the optional
  * HOST pointers.  Synchronises the stream.

@@ -16,7 +16,8 @@
 //     generates its A elements on the VALU (g/h windows and the per-k factors
 //     staged in LDS, as in the strip kernels) in the A-operand layout of the
 //     MFMA and contracts them against the W' tile (k x 16 masks) loaded from
-//     an L2-resident table two steps ahead of its use;
+//     an L2-resident table ahead of its use (two steps in float32, one in
+//     BF16x3, whose A generation per step is eight times longer);
 //   * float32 form: v_mfma_f32_16x16x4f32 (lane l holds row l % 16, k offset
 //     l / 16 of A and k offset l / 16, mask l % 16 of B);
 //     BF16x3 form: v_mfma_f32_16x16x32_bf16 (lane l holds row l % 16,
@@ -26,7 +27,8 @@
 //     bound the product's relative error by 3 * 2^-16, bfloat16 keeping 8
 //     significant bits);
 //   * every `flush` steps the float32 matrix-core accumulators are added into
-//     Kahan (sum, compensation) pairs;
+//     Kahan (sum, compensation) pairs (float32 form) or plain float32 sums
+//     (BF16x3, whose operand splits bound the error);
 //   * each mask's Xi goes to its own packed triangle [3][tri(lmax_m)], the
 //     store layout of the single-mask path; the MFMA output tile (lane l holds
 //     rows 4 (l/16) + i, mask l % 16) writes 16 consecutive l1 of a mask in
@@ -210,14 +212,21 @@ __device__ inline void row_constants(int A0, int d, int r, int (&gam)[TM], float
     }
 }
 
-template <int TM>
+// Add the matrix-core accumulators into the running sums: Kahan pairs
+// (COMP), or a plain float32 sum.
+template <int TM, bool COMP>
 __device__ inline void flush_acc(f4v (&acc)[TM][3], float (&ks)[TM][3][4], float (&kc)[TM][3][4]) {
 #pragma unroll
     for (int t = 0; t < TM; ++t)
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) kahan_add(ks[t][x][i], kc[t][x][i], acc[t][x][i]);
+            for (int i = 0; i < 4; ++i) {
+                if (COMP)
+                    kahan_add(ks[t][x][i], kc[t][x][i], acc[t][x][i]);
+                else
+                    ks[t][x][i] += acc[t][x][i];
+            }
             acc[t][x] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
         }
 }
@@ -319,7 +328,7 @@ batched_mfma_f32_kernel(BatchArgs a) {
             pb += kStepRows;
             if (++since_flush >= a.flush) {
                 since_flush = 0;
-                flush_acc<TM>(acc, ks, kc);
+                flush_acc<TM, true>(acc, ks, kc);
             }
         };
         // KC is a multiple of 8, so every chunk starts on an even step
@@ -328,7 +337,7 @@ batched_mfma_f32_kernel(BatchArgs a) {
             if (s0 + 4 < kc_n) step(s0 + 4, bB);
         }
     }
-    flush_acc<TM>(acc, ks, kc);
+    flush_acc<TM, true>(acc, ks, kc);
     store_xi<TM>(a, grp, d, A0, lane, ks, kc);
 }
 
@@ -413,9 +422,10 @@ batched_mfma_bf16x3_kernel(BatchArgs a) {
             for (int i = 0; i < 4; ++i) ks[t][x][i] = kc[t][x][i] = 0.0f;
         }
 
-    BTile bA, bB;
-    load_b(bA);
-    load_b(bB);
+    // one W' buffer, refilled for the next step right after the step's MFMAs
+    // have read it (the next step's A generation covers the load)
+    BTile bt;
+    load_b(bt);
 
     int since_flush = 0;
     for (int kch = k_org; kch <= kmax; kch += KC) {
@@ -478,16 +488,16 @@ batched_mfma_bf16x3_kernel(BatchArgs a) {
             load_b(bt);
             if (++since_flush >= a.flush) {
                 since_flush = 0;
-                flush_acc<TM>(acc, ks, kc);
+                flush_acc<TM, false>(acc, ks, kc);
             }
         };
         // KC is a multiple of 64, so every chunk starts on an even step
         for (int s0 = 0; s0 < KC && kch + s0 <= kmax; s0 += 64) {
-            step(s0, bA);
-            if (kch + s0 + 32 <= kmax) step(s0 + 32, bB);
+            step(s0, bt);
+            if (kch + s0 + 32 <= kmax) step(s0 + 32, bt);
         }
     }
-    flush_acc<TM>(acc, ks, kc);
+    flush_acc<TM, false>(acc, ks, kc);
     store_xi<TM>(a, grp, d, A0, lane, ks, kc);
 }
 
@@ -547,8 +557,8 @@ __global__ void batched_wprep_kernel(WPrepArgs a) {
 // Table geometry of a group of largest lmax L.
 inline int f32_rows(int L) { return 2 * L + 1 + kF32TailRows; }
 // A wavefront's last executed step starts at j <= jd + kmax <= L ((l3 - p) / 2 for
-// l3 <= 2L) and it has loaded the two steps after it: j <= L + 95.  A multiple of 8.
-inline int bf16_slots(int L) { return ((L + 96 + 7) / 8) * 8; }
+// l3 <= 2L) and it has loaded the step after it: j <= L + 63.  A multiple of 8.
+inline int bf16_slots(int L) { return ((L + 64 + 7) / 8) * 8; }
 inline size_t f32_table_elems(int L) { return 3ULL * (size_t)f32_rows(L) * kGroup; }
 inline size_t bf16_table_elems(int L) { return 3ULL * 2 * 2 * kGroup * (size_t)bf16_slots(L); }
 

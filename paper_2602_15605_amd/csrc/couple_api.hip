@@ -298,7 +298,9 @@ int upload_edges(couple_ctx* ctx, const int* bin_edges, int n_bins, hipStream_t 
 
 // One mask of a band-limited call, edges (if any) already on the device.
 int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const double* W_TP, const double* W_PP,
-             int lmax, unsigned spectra, int precision, bool binned, int n_bins, double* out, hipStream_t s) {
+             int lmax, unsigned spectra, int precision, const int* bin_edges, int n_bins, double* out,
+             hipStream_t s) {
+    const bool binned = bin_edges != nullptr;
     int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     const int hi = std::min(l3_hi, 2 * lmax);
@@ -315,7 +317,7 @@ int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const do
     if (rc) return rc;
     {
         Timed t(ctx, s, 2);
-        e = binned ? couple::launch_bin(ctx, lmax, dmax, src, n_out, ctx->edges_dev, n_bins, out, s)
+        e = binned ? couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, s)
                    : couple::launch_fill(ctx, lmax, dmax, src, n_out, out, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, binned ? "bin launch" : "fill launch");
@@ -336,12 +338,11 @@ int couple_band(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const
     rc = check_band(ctx, l3_lo, l3_hi, w_len, lmax, bin_edges, n_bins);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (bin_edges) {
+    if (bin_edges && n_bins > couple::kInlineBins) {
         rc = upload_edges(ctx, bin_edges, n_bins, s);
         if (rc) return rc;
     }
-    return band_one(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra, precision, bin_edges != nullptr, n_bins,
-                    out, s);
+    return band_one(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra, precision, bin_edges, n_bins, out, s);
 }
 
 int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
@@ -352,7 +353,7 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
     ctx->err.clear();
     if (n_masks < 1) return fail(ctx, COUPLE_EINVAL, "n_masks=%d < 1", n_masks);
     const bool need_tt = spectra & COUPLE_TT, need_tp = spectra & COUPLE_TE,
-               need_pp = spectra & (COUPLE_EE | COUPLE_BB);
+               need_pp = spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB);
     if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
         return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
     for (int m = 0; m < n_masks; ++m) {
@@ -366,7 +367,7 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
     int rc = check_band(ctx, l3_lo, l3_hi, w_len, lmax, bin_edges, n_bins);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (bin_edges) {
+    if (bin_edges && n_bins > couple::kInlineBins) {
         rc = upload_edges(ctx, bin_edges, n_bins, s);
         if (rc) return rc;
     }
@@ -375,7 +376,7 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
     const size_t per_mask = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
     for (int m = 0; m < n_masks; ++m) {
         rc = band_one(ctx, l3_lo, l3_hi, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
-                      need_pp ? W_PP[m] : nullptr, lmax, spectra, precision, bin_edges != nullptr, n_bins,
+                      need_pp ? W_PP[m] : nullptr, lmax, spectra, precision, bin_edges, n_bins,
                       out + m * per_mask, s);
         if (rc) return rc;
     }
@@ -459,7 +460,7 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
     if (rc) return rc;
     if (!w_len_i || !out) return fail(ctx, COUPLE_EINVAL, "w_len_i or out is NULL");
     const bool need_tt = spectra & COUPLE_TT, need_tp = spectra & COUPLE_TE,
-               need_pp = spectra & (COUPLE_EE | COUPLE_BB);
+               need_pp = spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB);
     if ((need_tt && !W_TT) || (need_tp && !W_TP) || (need_pp && !W_PP))
         return fail(ctx, COUPLE_EINVAL, "a requested spectrum's window array is NULL");
     const bool mfma = precision == COUPLE_MFMA_FP32 || precision == COUPLE_MFMA_BF16X3;
@@ -563,7 +564,7 @@ int couple_autotune_batched(couple_ctx* ctx, int precision, int n_masks, const i
     if (rc) return rc;
     static const int kTm[] = {1, 2, 4};
     // flush candidates: float32 steps are 4 k, BF16x3 steps 32 k
-    static const int kFlush[2][2] = {{4, 8}, {1, 2}};
+    static const int kFlush[2][2] = {{4, 8}, {2, 4}};
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -69,7 +69,7 @@ struct couple_ctx {
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
     // tile shape of the batched matrix-core kernels, [0] float32, [1] BF16x3
-    int batched_flush[2] = {8, 2};   // MFMA steps per Kahan flush
+    int batched_flush[2] = {8, 4};   // MFMA steps per accumulator flush
     int batched_tm[2] = {2, 2};      // 16-row tiles per wavefront
     std::string err;
     // measurement hook: event pairs recorded around each kernel
@@ -103,8 +103,11 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
 constexpr int kMaxOut = 5;
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                        double* out, hipStream_t s);
+// Up to kInlineBins bins the edges travel in the kernel arguments (no upload,
+// nothing to synchronise); longer lists are read from bin_edges_dev.
+constexpr int kInlineBins = 512;
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                      const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
+                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
 // One fill job: Xi store [3][tri(lmax)] (Xi for diagonals d <= dmax, 0 beyond)
 // and its n_out output matrices [n_out][lmax+1][lmax+1].  block0 is set by
 // launch_fill_jobs.

@@ -108,7 +108,9 @@ struct BinArgs {
     const double* xi;
     long long xi_stride;
     double* out;
-    const int* edges;            // device copy, n_bins + 1
+    const int* edges;            // device copy of n_bins + 1 edges (when n_bins > kInlineBins)
+    int inline_edges;            // edges are in edges_in
+    int edges_in[kInlineBins + 1];
     int n_bins;
     int lmax;
     int dmax;
@@ -120,8 +122,9 @@ __global__ void __launch_bounds__(kBinThreads)
 bin_kernel(BinArgs a) {
     __shared__ double red[kBinThreads];
     const int bb = blockIdx.x / a.n_bins, bc = blockIdx.x % a.n_bins;
-    const int r_lo = a.edges[bb], r_hi = a.edges[bb + 1];
-    const int c_lo = a.edges[bc], c_hi = a.edges[bc + 1];
+    const int* E = a.inline_edges ? a.edges_in : a.edges;
+    const int r_lo = E[bb], r_hi = E[bb + 1];
+    const int c_lo = E[bc], c_hi = E[bc + 1];
     const int nr = r_hi - r_lo, ncl = c_hi - c_lo;
     // smallest |l1 - l2| between the two bins
     const int gap = (c_lo >= r_hi) ? c_lo - (r_hi - 1) : (r_lo >= c_hi ? r_lo - (c_hi - 1) : 0);
@@ -191,12 +194,14 @@ hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spe
 }
 
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                      const int* bin_edges_dev, int n_bins, double* out, hipStream_t s) {
+                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, hipStream_t s) {
     BinArgs a;
     a.xi = ctx->xi;
     a.xi_stride = tri_size(lmax);
     a.out = out;
     a.edges = bin_edges_dev;
+    a.inline_edges = n_bins <= kInlineBins ? 1 : 0;
+    for (int i = 0; i <= kInlineBins; ++i) a.edges_in[i] = (a.inline_edges && i <= n_bins) ? bin_edges_host[i] : 0;
     a.n_bins = n_bins;
     a.lmax = lmax;
     a.dmax = dmax;

@@ -330,3 +330,45 @@ def test_workload2_fp32c_sampled_rows(torch_gpu, ctx, oracle_bulk):
     for i, s in enumerate(SPEC4):
         err = assert_parity(K[i][rows], Kr[i], Ar[i], TOL_FP32C, "workload2 fp32c %s" % s)
         _say("workload2 fp32c %s max rel err %.3e" % (s, err))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_graph_replay_matrix_and_band(torch_gpu, ctx, precision):
+    """couple_matrix (five spectra) and binned couple_band allocate nothing and
+    enqueue kernels only, so a captured graph replays to the eager result, replay
+    after replay, with eager work and synchronisations in between."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmax = 300
+    Ws = _windows(lmax, 61)
+    dW = [_gpu(torch, w) for w in Ws]
+    spectra = ("TT", "TE", "EE", "BB", "EB")
+    edges = [0, 3, 50, 51, 200, 301]
+    eager_k = couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=precision).clone()
+    eager_b = couple.couple_band(ctx, 2, 120, *dW, lmax, spectra=spectra, precision=precision,
+                                 bin_edges=edges).clone()
+    out_k = torch.empty_like(eager_k)
+    out_b = torch.empty_like(eager_b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=precision, out=out_k)
+        couple.couple_band(ctx, 2, 120, *dW, lmax, spectra=spectra, precision=precision, bin_edges=edges,
+                           out=out_b)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=precision, out=out_k)
+        couple.couple_band(ctx, 2, 120, *dW, lmax, spectra=spectra, precision=precision, bin_edges=edges,
+                           out=out_b)
+    for rep in range(4):
+        out_k.fill_(float("nan"))
+        out_b.fill_(float("nan"))
+        x = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_k, eager_k), rep
+        assert torch.equal(out_b, eager_b), rep
+        del x
