@@ -32,7 +32,7 @@ FLOP_PER_TRIPLE_TT = 5
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "strip_pol4_lmax6000_traffic.md")
-STRIP_SOURCES = [os.path.join(ROOT, "paper_2602_15605_amd", "csrc", f) for f in ("strip.hip", "couple_internal.hpp")]
+STRIP_SOURCES = [os.path.join(ROOT, "paper_2602_15605_amd", "csrc", f) for f in ("strip.hip", "strip_params.hpp")]
 
 
 def measured_traffic(kernel: str):

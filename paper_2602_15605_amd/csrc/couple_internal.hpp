@@ -9,31 +9,9 @@
 #include <vector>
 
 #include "couple.h"
+#include "strip_params.hpp"
 
 namespace couple {
-
-// Lanes of a wavefront on CDNA4.
-constexpr int kWave = 64;
-
-// Number of consecutive l1 values a lane of the strip kernel owns.  The
-// G/H windows slide by one per l3 step, so each step loads one new G and
-// one new H value per lane for R terms.
-constexpr int kStripR = 4;
-
-// l3 steps staged in LDS per chunk by the strip kernel.
-constexpr int kStripChunk = 128;
-
-// Zero guard band around the device copies of g(p) and 1/((2p+1)g(p)).
-constexpr int kTablePad = 64;
-
-// Offset of diagonal d of the packed upper-triangle store for lmax:
-// diagonal d holds Xi(l1, l1 + d) for l1 = 0 .. lmax - d.
-__host__ __device__ inline long long diag_offset(int lmax, int d) {
-    return (long long)d * (lmax + 1) - (long long)d * (d - 1) / 2;
-}
-__host__ __device__ inline long long tri_size(int lmax) {
-    return (long long)(lmax + 1) * (lmax + 2) / 2;
-}
 
 // Batched form: masks sorted by lmax and split into column groups of 16.
 constexpr int kMaxGroups = 4;          // up to 64 masks per call
@@ -92,7 +70,6 @@ hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
 // strip kernels (strip.hip): Xi on the packed upper triangle.
 //   mode kStripTT: Xi_TT; kStripPol: Xi_TT, Xi_TE, Xi_EE (even L);
 //   kStripEB: Xi_EB (odd L, fourth triangle).  l3 restricted to [l3_lo, l3_hi].
-enum { kStripTT = 0, kStripPol = 1, kStripEB = 2 };
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
                                 const double* wpp, int n, hipStream_t s);
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,

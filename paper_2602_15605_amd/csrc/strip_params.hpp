@@ -1,0 +1,35 @@
+// Parameters of the strip kernels and the packed-triangle indexing they share
+// with the fill, bin and batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace couple {
+
+// Lanes of a wavefront on CDNA4.
+constexpr int kWave = 64;
+
+// Number of consecutive l1 values a lane of the strip kernel owns.  The
+// G/H windows slide by one per l3 step, so each step loads one new G and
+// one new H value per lane for R terms.
+constexpr int kStripR = 4;
+
+// l3 steps staged in LDS per chunk by the strip kernel.
+constexpr int kStripChunk = 128;
+
+// Zero guard band around the device copies of g(p) and 1/((2p+1)g(p)).
+constexpr int kTablePad = 64;
+
+// Offset of diagonal d of the packed upper-triangle store for lmax:
+// diagonal d holds Xi(l1, l1 + d) for l1 = 0 .. lmax - d.
+__host__ __device__ inline long long diag_offset(int lmax, int d) {
+    return (long long)d * (lmax + 1) - (long long)d * (d - 1) / 2;
+}
+__host__ __device__ inline long long tri_size(int lmax) {
+    return (long long)(lmax + 1) * (lmax + 2) / 2;
+}
+
+// Strip kernel modes: Xi_TT; Xi_TT, Xi_TE, Xi_EE (even L); Xi_EB (odd L).
+enum { kStripTT = 0, kStripPol = 1, kStripEB = 2 };
+
+}  // namespace couple
