@@ -28,7 +28,10 @@
 //     lambda eta = sqrt(a (a-2) b (b-2)) = 1/(c_l1 c_l2).
 //
 // N' is an integer; here it is evaluated as N' = c (c - 2(a+b-1)) + a(a-2) + b(b-2)
-// with one fused multiply-add, exact in float64 while |N'| < 2^53.  The
+// with one fused multiply-add, rounded once while a(a-2) + b(b-2) < 2^53
+// (lmax <= 8000); beyond, that sum is not exact and N' cancels against it when
+// l1 << l2, so N' = t^2 - (2ab+1), t = c - (a+b-1), with 2ab+1 split exactly
+// into two doubles (see strip_fp64_kernel).  The
 // "(2,-2,0) recurrence" is thus an integer update of c along the strip.  The
 // three kernels then are
 //
@@ -59,7 +62,7 @@
 // one per step (one LDS read each per step for R terms); U_X(k) and c(k) are
 // read by the whole wave from one LDS address.  Terms with k > l1 read the
 // zero guard of the g window and vanish, so lanes of a wave share one trip
-// count.  Table windows are staged in LDS in chunks of kStripChunk steps
+// count.  Table windows are staged in LDS in chunks of 256 steps
 // with one padding word per R entries (a lane stride of R+1 doubles is free
 // of bank conflicts).  Work items are numbered longest first.
 #include "couple_internal.hpp"
@@ -130,10 +133,10 @@ __device__ inline bool strip_item(const StripArgs& a, int item, int* d_out, int*
     return true;
 }
 
-template <int R>
+template <int R, int KC>
 struct Win {
     static constexpr int kB = kWave * R;                // l1 per item
-    static constexpr int kLen = kB + kStripChunk - 1;   // window length
+    static constexpr int kLen = kB + KC - 1;            // window length
     static constexpr int kPhys = kLen + kLen / R + 1;   // with padding
     __device__ static inline int phys(int slot) { return slot + slot / R; }
 };
@@ -141,14 +144,19 @@ struct Win {
 // Kernel modes: TT only; TT + TE + EE (even L); EB (odd L).
 enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2 };
 
-template <int R, int MODE>
+// WIDE (lmax > kNarrowLmax): a(a-2) + b(b-2) exceeds 2^53 and N' cancels
+// against it when l1 << l2, so N' is taken as t^2 - (2ab + 1) with t exact and
+// 2ab + 1 = beta_hi + beta_lo split exactly: one more operation per term.
+constexpr int kNarrowLmax = 8000;
+
+template <int R, int MODE, bool WIDE>
 __global__ void __launch_bounds__(kWave)
 strip_fp64_kernel(StripArgs a) {
     constexpr bool POL = MODE == kModePol;
     constexpr bool EB = MODE == kModeEB;
-    using W = Win<R>;
+    constexpr int KC = kStripChunkF64;
+    using W = Win<R, KC>;
     constexpr int B = W::kB;
-    constexpr int KC = kStripChunk;
     __shared__ double s_g[W::kPhys];
     __shared__ double s_h[W::kPhys];
     __shared__ double4 s_u[KC];
@@ -164,16 +172,25 @@ strip_fp64_kernel(StripArgs a) {
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
 
-    // gam2, kap: N' = c (c - gam2) + kap (even L); for EB: sig(sig+1) and mu
-    double tt[R], te[R], ee[R], gam2[R], kap[R], gw[R], hw[R];
+    // even L: N' = c (c - gam2) + kap, every piece exact while lmax <= kNarrowLmax;
+    //   WIDE: N' = t^2 - kap - blo, t = c - gam2, gam2 = a + b - 1, kap + blo = 2ab + 1.
+    // EB: gam2 = sig(sig+1), kap = mu.
+    double tt[R], te[R], ee[R], gam2[R], kap[R], blo[R], gw[R], hw[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         tt[j] = te[j] = ee[j] = 0.0;
+        blo[j] = 0.0;
         const long long l1 = l1_0 + j, l2 = l1 + d;
         if (EB) {
             const long long sg = l1 + l2 + 1, tau = sg + 1;
             gam2[j] = (double)(sg * (sg + 1));
             kap[j] = (double)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
+        } else if (WIDE) {
+            const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+            const long long beta = 2 * aa * bb + 1;
+            gam2[j] = (double)(aa + bb - 1);
+            kap[j] = (double)beta;
+            blo[j] = (double)(beta - (long long)kap[j]);
         } else {
             const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
             gam2[j] = (double)(2 * (aa + bb - 1));
@@ -258,8 +275,14 @@ strip_fp64_kernel(StripArgs a) {
                     }
                     tt[j] = __builtin_fma(uu.x, P, tt[j]);
                     if (POL) {
-                        const double dc = uu.w - gam2[j];
-                        const double N = __builtin_fma(uu.w, dc, kap[j]);
+                        double N;
+                        if (WIDE) {
+                            const double t = uu.w - gam2[j];
+                            N = __builtin_fma(t, t, -kap[j]) - blo[j];
+                        } else {
+                            const double dc = uu.w - gam2[j];
+                            N = __builtin_fma(uu.w, dc, kap[j]);
+                        }
                         const double y = P * N;
                         te[j] = __builtin_fma(uu.y, y, te[j]);
                         const double z = y * N;
@@ -300,9 +323,10 @@ strip_fp64_kernel(StripArgs a) {
 //       once to float32,
 //   N' = t^2 - (2ab + 1) with t = c - (a + b - 1).  The subtraction cancels
 //       (t is small when l1 << l2), so t is formed from exact pieces: per lane
-//       and chunk the integer T = c(chunk start) - (a + b - 1) is split into
+//       and split the integer T = c(split start) - (a + b - 1) is split into
 //       float32 T_hi + T_lo exactly, the staged per-step value is the integer
-//       D(k) = c(k) - c(chunk start) (|D| < 2^24, exact in float32), and
+//       D(k) = c(k) - c(split start) (|D| < 2^24, exact in float32; the split
+//       is rebased every kStripRebase steps), and
 //       t = T_hi + (D + T_lo) is rounded once -- two float32 adds instead of an
 //       integer subtraction and a half-rate int-to-float conversion.  Then
 //       one fused multiply-add gives N'.
@@ -316,11 +340,12 @@ __global__ void __launch_bounds__(kWave)
 strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
     constexpr bool POL = MODE == kModePol;
     constexpr bool EB = MODE == kModeEB;
-    using W = Win<R>;
+    constexpr int KC = kStripChunkF32;
+    using W = Win<R, KC>;
     constexpr int B = W::kB;
-    constexpr int KC = kStripChunk;
     constexpr int G = kCompBlock;
-    static_assert(KC % G == 0 && G % R == 0, "chunk must hold whole blocks");
+    constexpr int RB = kStripRebase;
+    static_assert(KC % RB == 0 && RB % G == 0 && G % R == 0, "chunk must hold whole splits and blocks");
     __shared__ float s_g[W::kPhys];
     __shared__ float s_h[W::kPhys];
     __shared__ float4 s_u[KC];
@@ -377,7 +402,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             if (s < kc) {
                 const int k = k0 + s;
                 const int l3 = de + 2 * k;
-                const int l3c = de + 2 * k0;
+                const int l3c = de + 2 * (k0 + s / RB * RB);     // l3 at this step's split
                 const double gg = a.g[k] * a.g[de + k];
                 if (EB) {
                     const long long c = (long long)l3 * (l3 + 1);
@@ -404,25 +429,27 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
-        // even L: t = T + D(k) with T = c(d + 2 k0) - (a + b - 1) = T_hi + T_lo exactly.
-        // EB: f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c(de + 2 k0), and
-        //     f3 = c + mu = T3 + D(k), T3 = c(de + 2 k0) + mu, both split the same way.
         float thi[R], tlo[R], t3hi[R], t3lo[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int l3c = de + 2 * k0;
-            const int cc = l3c * (l3c + 1);
-            const int T = EB ? gam[j] - cc : cc - gam[j];
-            thi[j] = (float)T;
-            tlo[j] = (float)(T - (int)thi[j]);
-            const int T3 = cc + mu[j];
-            t3hi[j] = (float)T3;
-            t3lo[j] = (float)(T3 - (int)t3hi[j]);
-        }
         const int kc_r = (kc + G - 1) / G * G;
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
         const float* ph = s_h + (R + 1) * lane + (R - 1);
         for (int sb = 0; sb < kc_r; sb += G) {
+            if (sb % RB == 0) {
+                // even L: t = T + D(k), T = c(l3 at the split) - (a + b - 1) = T_hi + T_lo exactly.
+                // EB: f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c(l3 at the split), and
+                //     f3 = c + mu = T3 + D(k), T3 = c(l3 at the split) + mu, both split the same way.
+                const int l3c = de + 2 * (k0 + sb);
+                const int cc = l3c * (l3c + 1);
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int T = EB ? gam[j] - cc : cc - gam[j];
+                    thi[j] = (float)T;
+                    tlo[j] = (float)(T - (int)thi[j]);
+                    const int T3 = cc + mu[j];
+                    t3hi[j] = (float)T3;
+                    t3lo[j] = (float)(T3 - (int)t3hi[j]);
+                }
+            }
             float bt[R], bte[R], bee[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) bt[j] = bte[j] = bee[j] = 0.0f;
@@ -556,11 +583,13 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeTT>), grid, block, 0, s, a, gf, hf);
     } else {
         if (mode == kStripEB)
-            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEB>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEB, false>), grid, block, 0, s, a);
+        else if (mode == kStripPol && lmax > kNarrowLmax)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol, true>), grid, block, 0, s, a);
         else if (mode == kStripPol)
-            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol, false>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }

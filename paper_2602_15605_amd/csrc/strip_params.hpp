@@ -14,8 +14,14 @@ constexpr int kWave = 64;
 // one new H value per lane for R terms.
 constexpr int kStripR = 4;
 
-// l3 steps staged in LDS per chunk by the strip kernel.
-constexpr int kStripChunk = 128;
+// l3 steps staged in LDS per chunk by the float64 and float32 strip kernels.
+constexpr int kStripChunkF64 = 256;
+constexpr int kStripChunkF32 = 256;
+
+// float32 strip kernel: steps per exact split of t = c - (a + b - 1).  Within
+// one split the staged D(k) = c(l3) - c(l3 at the split) is below
+// 254 (2 l3 + 255) < 2^24 for l3 <= 2 x 16384, hence exact in float32.
+constexpr int kStripRebase = 128;
 
 // Zero guard band around the device copies of g(p) and 1/((2p+1)g(p)).
 constexpr int kTablePad = 64;

@@ -372,3 +372,30 @@ def test_graph_replay_matrix_and_band(torch_gpu, ctx, precision):
         assert torch.equal(out_k, eager_k), rep
         assert torch.equal(out_b, eager_b), rep
         del x
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32c", TOL_FP32C)])
+def test_lmax_limit_sampled_rows(torch_gpu, oracle_bulk, precision, tol):
+    """lmax = COUPLE_LMAX_LIMIT (16384), all five spectra, sampled rows including
+    l1 = lmax.  l3 reaches 2 lmax = 32768, where the FP32C kernel's exact t split
+    needs its rebasing and FP64 evaluates N' beyond 2^53.  Windows with
+    l_c = lmax / 2 keep every K element inside the float32 range."""
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    lmax = couple.LMAX_LIMIT
+    W = [synth.window_spectrum(lmax, lmax / 2.0, 7000 + s) for s in range(3)]
+    spectra = ("TT", "TE", "EE", "BB", "EB")
+    rows = np.array([2, 3000, 9001, lmax - 1, lmax])
+    c = couple.couple_init(lmax)
+    try:
+        dW = [_gpu(torch, w) for w in W]
+        K = couple.couple_matrix(c, *dW, lmax, spectra=spectra, precision=precision)
+        got = K[:, torch.as_tensor(rows).cuda(), :].cpu().numpy()
+        del K
+    finally:
+        couple.couple_free(c)
+    torch.cuda.empty_cache()
+    Kr, Ar = oracle_bulk.coupling_rows(lmax, *W, rows=rows, spectra=spectra)
+    for i, s in enumerate(spectra):
+        err = assert_parity(got[i], Kr[i], Ar[i], tol, "lmax %d %s %s" % (lmax, precision, s))
+        _say("lmax %d %s %s max rel err %.3e" % (lmax, precision, s, err))
