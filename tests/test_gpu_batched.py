@@ -191,3 +191,26 @@ def test_batched_graph_replay(torch_gpu, ctx, precision):
         for m in range(len(lmaxes)):
             assert torch.equal(outs[m], eager[m]), (rep, m)
         del x
+
+
+@pytest.mark.parametrize("precision,tol", MFMA)
+def test_batched_64_masks_four_groups(torch_gpu, ctx, oracle_bulk, precision, tol):
+    """The largest batch: 64 masks in four column groups (64 fill jobs), with
+    repeated, tiny (0, 1) and equal lmax values; every mask's full matrix checked."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    rng = np.random.default_rng(64)
+    lmaxes = [int(x) for x in rng.integers(0, 90, 60)] + [0, 1, 89, 89]
+    _say("64 masks %s, lmax %d..%d" % (precision, min(lmaxes), max(lmaxes)))
+    Ws = _rand_windows(lmaxes, 65)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    couple.couple_reserve_batched(ctx, lmaxes)
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, L in enumerate(lmaxes):
+        K = outs[m].cpu().numpy()
+        Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], spectra=SPEC4)
+        for i, s in enumerate(SPEC4):
+            worst = max(worst, assert_parity(K[i], Kr[i], Ar[i], tol, "mask %d lmax %d %s" % (m, L, s)))
+    _say("64 masks %s: max rel err %.3e" % (precision, worst))
