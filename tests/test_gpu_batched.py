@@ -67,17 +67,24 @@ def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk, precision, tol):
     _say("batched small %s: max rel err %.3e" % (precision, worst))
 
 
-@pytest.mark.parametrize("precision,tol", MFMA)
-def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, tol):
+@pytest.mark.parametrize("precision,tol,flush", [("mfma_fp32", TOL_FP32C, 4), ("mfma_fp32", TOL_FP32C, 8),
+                                                  ("mfma_bf16x3", TOL_BF16X3, 4)])
+def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, tol, flush):
+    """The 32-mask workload at every flush interval the autotuner may pick."""
     from paper_2602_15605_amd import couple, synth
     torch = torch_gpu
     lmaxes = [int(x) for x in synth.batched_lmaxes()]
-    _say("workload3 batched %s" % precision)
+    _say("workload3 batched %s flush %d" % (precision, flush))
     Ws = [synth.workload_windows(3, mask=m) for m in range(len(lmaxes))]
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
-    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
-    torch.cuda.synchronize()
+    saved = couple.couple_get_batched_tiles(ctx, precision=precision)
+    couple.couple_set_batched_tiles(ctx, 2, flush, precision=precision)
+    try:
+        outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
+        torch.cuda.synchronize()
+    finally:
+        couple.couple_set_batched_tiles(ctx, *saved, precision=precision)
     worst = {s: 0.0 for s in SPEC4}
     for m, L in enumerate(lmaxes):
         rows = synth.sample_rows(L, fraction=0.01, seed=3000 + m, minimum=5)
@@ -85,7 +92,7 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, 
         Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], rows=rows, spectra=SPEC4)
         for i, s in enumerate(SPEC4):
             worst[s] = max(worst[s], assert_parity(got[i], Kr[i], Ar[i], tol, "mask %d lmax %d %s" % (m, L, s)))
-    _say("workload3 batched %s max rel err: " % precision + ", ".join("%s %.3e" % kv for kv in worst.items()))
+    _say("workload3 batched %s flush %d max rel err: " % (precision, flush) + ", ".join("%s %.3e" % kv for kv in worst.items()))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
