@@ -331,10 +331,13 @@ batched_mfma_f32_kernel(BatchArgs a) {
                 flush_acc<TM, true>(acc, ks, kc);
             }
         };
-        // KC is a multiple of 8, so every chunk starts on an even step
+        // KC is a multiple of 8, so every chunk starts on an even step.  Steps
+        // run in unconditional pairs, so the compiler sees both W' buffers in
+        // flight at the loop head: a step past kmax has S(k) = 0 (staged zero)
+        // and adds nothing, and its W' loads stay inside the zero tail rows.
         for (int s0 = 0; s0 < kc_n; s0 += 8) {
             step(s0, bA);
-            if (s0 + 4 < kc_n) step(s0 + 4, bB);
+            step(s0 + 4, bB);
         }
     }
     flush_acc<TM, true>(acc, ks, kc);
