@@ -1,4 +1,4 @@
-// Batched form: many windows (masks) of uneven lmax in one launch.
+// Batched form: many windows (masks) of uneven lmax in one contraction launch.
 //
 // For a set of masks the l3 reduction is a contraction
 //
@@ -76,7 +76,7 @@ struct BatchArgs {
     const void* wtab;               // W' tables of every group
     double* xi;                     // Xi workspace base
     int g_len, h_len;
-    int flush;                      // MFMA steps per Kahan flush
+    int flush;                      // MFMA steps per accumulator flush
 };
 
 // Waves per SIMD the register allocation is held to (the largest that does

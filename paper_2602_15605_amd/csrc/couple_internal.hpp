@@ -23,7 +23,7 @@ struct BatchPlan {
     int lmax[kMaxGroups][kMaskGroup];
     const double* w[kMaxGroups][3][kMaskGroup];    // W_TT, W_TP, W_PP (NULL: unused)
     double* out[kMaxGroups][kMaskGroup];
-    int flush = 8;                                  // MFMA steps per Kahan flush
+    int flush = 8;                                  // MFMA steps per accumulator flush
     int tm = 2;                                     // 16-row tiles per wavefront (1, 2, 4)
 };
 

@@ -399,3 +399,19 @@ def test_lmax_limit_sampled_rows(torch_gpu, oracle_bulk, precision, tol):
     for i, s in enumerate(spectra):
         err = assert_parity(got[i], Kr[i], Ar[i], tol, "lmax %d %s %s" % (lmax, precision, s))
         _say("lmax %d %s %s max rel err %.3e" % (lmax, precision, s, err))
+
+
+@pytest.mark.parametrize("n_bins", [512, 701])
+def test_unit_bins_equal_unbinned(torch_gpu, ctx, n_bins):
+    """Bins one multipole wide reproduce the unbinned matrix bitwise, both for
+    bin lists carried in the kernel arguments (<= 512 bins) and for longer lists
+    staged through the context's pinned buffer."""
+    from paper_2602_15605_amd import couple
+    lmax = n_bins - 1
+    Ws = _windows(lmax, 91)
+    dW = [_gpu(torch_gpu, w) for w in Ws]
+    spectra = ("TT", "TE", "EE", "BB", "EB")
+    K = couple.couple_band(ctx, 1, 200, *dW, lmax, spectra=spectra)
+    Kb = couple.couple_band(ctx, 1, 200, *dW, lmax, spectra=spectra, bin_edges=np.arange(lmax + 2))
+    assert Kb.shape == K.shape
+    assert torch_gpu.equal(Kb, K)
