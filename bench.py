@@ -86,6 +86,45 @@ def _timed(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def run_context(torch, couple, synth):
+    """Context numbers beside the headline (never `value`):
+    * the paper's own GPU comparison point: K^TT alone and K^EE alone at
+      lmax = 10^4 in FP64 (the paper times each on an A100);
+    * end to end at lmax = 6000, FP32C: couple_init (tables), W host -> device,
+      couple_matrix, K device -> host (pageable), wall clock."""
+    out = {}
+    L = 10000
+    W = [synth.window_spectrum(L, 2500.0, 9000 + s) for s in range(3)]   # a full (not band-limited) window
+    ctx = couple.couple_init(L)
+    dW = [torch.as_tensor(w).cuda() for w in W]
+    res = torch.empty((1, L + 1, L + 1), dtype=torch.float64, device="cuda")
+    for spec in ("TT", "EE"):
+        args = [dW[0] if spec == "TT" else None, None, dW[2] if spec == "EE" else None]
+        ms = _timed(torch, lambda: couple.couple_matrix(ctx, *args, L, spectra=(spec,), precision="fp64", out=res),
+                    3, 1)
+        out["single_spectrum_lmax10000_fp64_" + spec] = {
+            "ms_per_call": ms, "k_elements_per_s": (L + 1) ** 2 / (ms * 1e-3),
+            "note": "the paper times K^TT (0.63 s) and K^EE (3.2 s) at lmax=10^4 on an A100 (kernel only)"}
+    del res
+    couple.couple_free(ctx)
+    torch.cuda.synchronize()
+    lmax = 6000
+    Wh = synth.workload_windows(2, lmax=lmax)
+    t0 = time.perf_counter()
+    ctx = couple.couple_init(lmax)
+    dW = [torch.as_tensor(w).cuda() for w in Wh]
+    K = couple.couple_matrix(ctx, *dW, lmax, spectra=("TT", "TE", "EE", "BB"), precision="fp32c")
+    Kh = K.cpu()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["end_to_end_lmax6000_fp32c"] = {
+        "ms": 1e3 * dt, "k_elements_per_s": 4 * (lmax + 1) ** 2 / dt,
+        "includes": "couple_init (tables), W host->device, couple_matrix, 1.15 GB K device->host (pageable)"}
+    del K, Kh
+    couple.couple_free(ctx)
+    return out
+
+
 def run_extras(torch, couple, synth, args):
     """The band-limited and batched workloads, timed the same way (device time
     per call, inputs resident); reported beside the headline, not as it."""
@@ -287,6 +326,8 @@ def main():
                 results[prec]["max_rel_err"] = errs
 
     extras = {} if args.no_extras else run_extras(torch, couple, synth, args)
+    if not args.no_extras:
+        extras.update(run_context(torch, couple, synth))
 
     head = "fp32c" if "ms_per_step" in results.get("fp32c", {}) else "fp64"
     h = results[head]
