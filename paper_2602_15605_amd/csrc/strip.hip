@@ -330,10 +330,16 @@ strip_fp64_kernel(StripArgs a) {
 //       t = T_hi + (D + T_lo) is rounded once -- two float32 adds instead of an
 //       integer subtraction and a half-rate int-to-float conversion.  Then
 //       one fused multiply-add gives N'.
-// Accumulation: each lane sums kCompBlock consecutive terms with float32 FMA
-// and adds the block sum into a Kahan (sum, compensation) pair in float32;
-// the pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.
+// Accumulation, three levels per spectrum and lane-owned l1: kCompBlock
+// consecutive terms are summed with float32 FMA into a block sum; block sums
+// are added plainly into a mid sum; every kCompPeriod steps (and at the end of
+// a chunk) the mid sum enters a Kahan (sum, compensation) pair in float32.
+// The pair is combined and rescaled by s = c_l1 c_l2 / 2 in float64.  The
+// mid level holds at most kCompPeriod / kCompBlock block sums, so its rounding
+// stays at the size of the per-term rounding while the Kahan step runs once
+// per 64 terms instead of once per 16.
 constexpr int kCompBlock = 4 * kStripR;
+constexpr int kCompPeriod = 64;
 
 template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
@@ -345,7 +351,9 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     constexpr int B = W::kB;
     constexpr int G = kCompBlock;
     constexpr int RB = kStripRebase;
-    static_assert(KC % RB == 0 && RB % G == 0 && G % R == 0, "chunk must hold whole splits and blocks");
+    constexpr int CP = kCompPeriod;
+    static_assert(KC % RB == 0 && RB % G == 0 && G % R == 0 && CP % G == 0,
+                  "chunk must hold whole splits and blocks");
     __shared__ float s_g[W::kPhys];
     __shared__ float s_h[W::kPhys];
     __shared__ float4 s_u[KC];
@@ -361,14 +369,16 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
 
-    // Kahan pairs (sum, compensation) per spectrum and lane-owned l1
+    // Kahan pairs (sum, compensation) and mid sums per spectrum and lane-owned l1
     float kt[R], kte[R], kee[R], ct[R], cte[R], cee[R];
+    float mt[R], mte[R], mee[R];
     float gw[R], hw[R], beta[R];
     // even L: gam = a + b - 1, beta = 2ab + 1; EB: gam = sig(sig+1), mu
     int gam[R], mu[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         kt[j] = kte[j] = kee[j] = ct[j] = cte[j] = cee[j] = 0.0f;
+        mt[j] = mte[j] = mee[j] = 0.0f;
         const long long l1 = l1_0 + j, l2 = l1 + d;
         if (EB) {
             const long long sg = l1 + l2 + 1, tau = sg + 1;
@@ -487,24 +497,36 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     }
                 }
             }
-            // Kahan step: add the block sums
+            // block sums into the mid sums
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                mt[j] += bt[j];
+                if (POL) {
+                    mte[j] += bte[j];
+                    mee[j] += bee[j];
+                }
+            }
+            if ((sb + G) % CP != 0 && sb + G < kc_r) continue;
+            // Kahan step: mid sums into the pairs
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 {
-                    const float yv = bt[j] - ct[j];
+                    const float yv = mt[j] - ct[j];
                     const float tv = kt[j] + yv;
                     ct[j] = (tv - kt[j]) - yv;
                     kt[j] = tv;
+                    mt[j] = 0.0f;
                 }
                 if (POL) {
-                    const float yv = bte[j] - cte[j];
+                    const float yv = mte[j] - cte[j];
                     const float tv = kte[j] + yv;
                     cte[j] = (tv - kte[j]) - yv;
                     kte[j] = tv;
-                    const float yw = bee[j] - cee[j];
+                    const float yw = mee[j] - cee[j];
                     const float tw = kee[j] + yw;
                     cee[j] = (tw - kee[j]) - yw;
                     kee[j] = tw;
+                    mte[j] = mee[j] = 0.0f;
                 }
             }
         }
