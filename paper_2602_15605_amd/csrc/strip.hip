@@ -329,7 +329,11 @@ strip_fp64_kernel(StripArgs a) {
 //       is rebased every kStripRebase steps), and
 //       t = T_hi + (D + T_lo) is rounded once -- two float32 adds instead of an
 //       integer subtraction and a half-rate int-to-float conversion.  Then
-//       one fused multiply-add gives N'.
+//       one fused multiply-add gives N'.  Only a lane's first row takes the
+//       split; row j uses t_j = t_0 - (gam_j - gam_0), gam = a + b - 1, whose
+//       integer offset (below 2^19) is exact in float32: the subtraction is
+//       exact while |t_0| < 2^24 and otherwise adds one rounding of a value
+//       within 3 % of |t_0|, so t_j stays within 2^-23 relative.
 // Accumulation, three levels per spectrum and lane-owned l1: kCompBlock
 // consecutive terms are summed with float32 FMA into a block sum; block sums
 // are added plainly into a mid sum; every kCompPeriod steps (and at the end of
@@ -375,6 +379,8 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     float gw[R], hw[R], beta[R];
     // even L: gam = a + b - 1, beta = 2ab + 1; EB: gam = sig(sig+1), mu
     int gam[R], mu[R];
+    // exact offsets of rows j from the lane's first row
+    float dg[R], dm[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         kt[j] = kte[j] = kee[j] = ct[j] = cte[j] = cee[j] = 0.0f;
@@ -391,6 +397,12 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             mu[j] = 0;
             beta[j] = (float)(2.0 * (double)aa * (double)bb + 1.0);
         }
+    }
+
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        dg[j] = (float)(gam[j] - gam[0]);
+        dm[j] = (float)(mu[j] - mu[0]);
     }
 
     const double* wtt = a.wp;
@@ -439,7 +451,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
-        float thi[R], tlo[R], t3hi[R], t3lo[R];
+        float thi = 0.0f, tlo = 0.0f, t3hi = 0.0f, t3lo = 0.0f;   // first row's split
         const int kc_r = (kc + G - 1) / G * G;
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
         const float* ph = s_h + (R + 1) * lane + (R - 1);
@@ -450,15 +462,12 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                 //     f3 = c + mu = T3 + D(k), T3 = c(l3 at the split) + mu, both split the same way.
                 const int l3c = de + 2 * (k0 + sb);
                 const int cc = l3c * (l3c + 1);
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const int T = EB ? gam[j] - cc : cc - gam[j];
-                    thi[j] = (float)T;
-                    tlo[j] = (float)(T - (int)thi[j]);
-                    const int T3 = cc + mu[j];
-                    t3hi[j] = (float)T3;
-                    t3lo[j] = (float)(T3 - (int)t3hi[j]);
-                }
+                const int T = EB ? gam[0] - cc : cc - gam[0];
+                thi = (float)T;
+                tlo = (float)(T - (int)thi);
+                const int T3 = cc + mu[0];
+                t3hi = (float)T3;
+                t3lo = (float)(T3 - (int)t3hi);
             }
             float bt[R], bte[R], bee[R];
 #pragma unroll
@@ -476,18 +485,21 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
                     hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
                     const float4 uu = pu[u];
+                    // first row exact split; rows j > 0 add their exact integer offsets
+                    const float t0 = thi + (uu.w + tlo);
+                    const float f10 = thi + (tlo - uu.w), f30 = t3hi + (uu.w + t3lo);
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const float P = gw[j] * hw[j];
                         if (EB) {
-                            const float f1 = thi[j] + (tlo[j] - uu.w);
-                            const float f3 = t3hi[j] + (uu.w + t3lo[j]);
+                            const float f1 = j == 0 ? f10 : f10 + dg[j];
+                            const float f3 = j == 0 ? f30 : f30 + dm[j];
                             bt[j] = __builtin_fmaf(uu.x, P * ((f1 * f3) * f3), bt[j]);
                             continue;
                         }
                         bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
                         if (POL) {
-                            const float t = thi[j] + (uu.w + tlo[j]);
+                            const float t = j == 0 ? t0 : t0 - dg[j];
                             const float N = __builtin_fmaf(t, t, -beta[j]);
                             const float y = P * N;
                             bte[j] = __builtin_fmaf(uu.y, y, bte[j]);
