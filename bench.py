@@ -143,6 +143,13 @@ def run_extras(torch, couple, synth, args):
                                                               bin_edges=edges, out=res), steps, warm)
         out["band_lmax10000_cut1000_8masks_binned_" + prec] = {
             "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200}
+    # the same band-limited call writing the symmetric kernels Xi (the covariance kernels when
+    # the windows are squared-mask spectra)
+    ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,
+                                                          spectra=("TT", "EE", "BB"), precision="fp32c",
+                                                          bin_edges=edges, out=res, xi=True), steps, warm)
+    out["band_lmax10000_cut1000_8masks_binned_xi_fp32c"] = {
+        "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200, "output": "Xi"}
     couple.couple_free(ctx)
     del dW, res
     # batched: 32 masks, lmax uniform in [500, 4000], 4 spectra, matrix-core contraction

@@ -56,8 +56,14 @@ enum couple_spectrum {
     COUPLE_TE = 2,
     COUPLE_EE = 4,
     COUPLE_BB = 8,
-    COUPLE_EB = 16  /* odd-L leakage kernel of App. A: S^EB = [(1-(-1)^L)/2]^2 (l1 l2 l3; -2 2 0)^2
+    COUPLE_EB = 16, /* odd-L leakage kernel of App. A: S^EB = [(1-(-1)^L)/2]^2 (l1 l2 l3; -2 2 0)^2
                        with W_PP (the E-B mixing block of the MASTER polarization matrix) */
+    COUPLE_XI = 256 /* output-form flag, OR-ed into spectra: write the symmetric kernels
+                       Xi_X(l1, l2) of App. A instead of K^X = (2 l2 + 1) Xi_X, same layout.
+                       Evaluated on the power spectrum of the squared mask, these are the
+                       kernels of the approximate pseudo-C_l covariance (Sec. 2; band-limited
+                       form Sec. 4.3).  For the same inputs and precision, K^X equals the
+                       float64 product (2 l2 + 1) * Xi_X bit for bit. */
 };
 
 /* arithmetic of the l3 reduction */
@@ -105,6 +111,7 @@ const char *couple_last_error(const couple_ctx *ctx);
  *   W_TT, W_TP, W_PP : device float64 window spectra W_l, l = 0 .. w_len-1.
  *                      Only those the requested spectra use must be non-NULL
  *                      (TT -> W_TT, TE -> W_TP, EE/BB/EB -> W_PP).
+ *                      With COUPLE_XI in spectra, Xi_X is written instead of K^X.
  *   w_len            : >= 2*lmax + 1 (W_L is needed for L <= 2 lmax, Sec. 4).
  *   lmax             : 0 <= lmax <= lmax_max of ctx.
  *   spectra          : non-empty OR of COUPLE_TT/TE/EE/BB/EB; output i is the

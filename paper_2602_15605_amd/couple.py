@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcouple.so")
 
 COUPLE_OK, COUPLE_EINVAL, COUPLE_ENOMEM, COUPLE_EDEVICE, COUPLE_ENOTSUP = 0, -1, -2, -3, -4
 TT, TE, EE, BB, EB = 1, 2, 4, 8, 16
+XI = 256            # output-form flag: the symmetric kernels Xi_X instead of K^X = (2 l2 + 1) Xi_X
 SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB, "EB": EB}
 SPECTRUM_ORDER = ("TT", "TE", "EE", "BB", "EB")
 PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2, "mfma_bf16x3": 3}
@@ -117,13 +118,14 @@ def couple_free(ctx: Context) -> None:
         ctx.handle = None
 
 
-def _spectra_bits(spectra) -> int:
+def _spectra_bits(spectra, xi=False) -> int:
     if isinstance(spectra, int):
-        return spectra
-    bits = 0
-    for s in spectra:
-        bits |= SPECTRUM_BITS[s]
-    return bits
+        bits = spectra
+    else:
+        bits = 0
+        for s in spectra:
+            bits |= SPECTRUM_BITS[s]
+    return bits | (XI if xi else 0)
 
 
 def _n_spec(bits: int) -> int:
@@ -147,14 +149,15 @@ def _stream_handle(stream):
 
 
 def couple_matrix(ctx, W_TT, W_TP, W_PP, lmax, spectra=("TT", "TE", "EE", "BB"), precision="fp64",
-                  out=None, stream=None):
+                  out=None, stream=None, xi=False):
     """K matrices [n_spec, lmax+1, lmax+1] (float64 tensor on the GPU).
 
     ``W_*`` are float64 GPU tensors of length >= 2*lmax+1 (None where unused).
+    ``xi=True`` returns the symmetric kernels Xi_X (COUPLE_XI) instead of K^X.
     Asynchronous on ``stream`` (default: torch's current stream).
     """
     import torch
-    bits = _spectra_bits(spectra)
+    bits = _spectra_bits(spectra, xi)
     ns = _n_spec(bits)
     if out is None:
         dev = next(w.device for w in (W_TT, W_TP, W_PP) if w is not None)
@@ -172,14 +175,15 @@ def couple_matrix(ctx, W_TT, W_TP, W_PP, lmax, spectra=("TT", "TE", "EE", "BB"),
 
 
 def couple_band(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT", "EE", "BB"), precision="fp64",
-                bin_edges=None, out=None, stream=None):
+                bin_edges=None, out=None, stream=None, xi=False):
     """Band-limited K (only l3_lo <= l3 <= l3_hi in the sum), optionally binned.
 
     ``bin_edges``: host sequence of n_bins+1 increasing multipoles, or None.
+    ``xi=True``: the symmetric kernels Xi_X instead of K^X.
     Returns [n_spec, lmax+1, lmax+1] or [n_spec, n_bins, n_bins].
     """
     import torch
-    bits = _spectra_bits(spectra)
+    bits = _spectra_bits(spectra, xi)
     ns = _n_spec(bits)
     edges = None
     n_bins = 0
@@ -209,13 +213,13 @@ def _ptr_array(tensors, name):
 
 
 def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT", "EE", "BB"),
-                        precision="fp64", bin_edges=None, out=None, stream=None):
+                        precision="fp64", bin_edges=None, out=None, stream=None, xi=False):
     """couple_band for a list of masks: ``W_*`` are lists of GPU tensors (or None).
 
     Returns [n_masks, n_spec, ...] with the couple_band layout per mask.
     """
     import torch
-    bits = _spectra_bits(spectra)
+    bits = _spectra_bits(spectra, xi)
     ns = _n_spec(bits)
     lists = [W_TT, W_TP, W_PP]
     n_masks = next(len(w) for w in lists if w is not None)
@@ -246,14 +250,14 @@ def couple_reserve_batched(ctx, lmax_list) -> None:
 
 
 def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE", "EE", "BB"),
-                          precision="mfma_fp32", outs=None, stream=None):
+                          precision="mfma_fp32", outs=None, stream=None, xi=False):
     """Coupling matrices for a list of masks of uneven lmax in one call.
 
     ``W_*`` are lists of float64 GPU tensors (or None); returns a list of
-    [n_spec, lmax_m+1, lmax_m+1] tensors.
+    [n_spec, lmax_m+1, lmax_m+1] tensors (Xi_X with ``xi=True``).
     """
     import torch
-    bits = _spectra_bits(spectra)
+    bits = _spectra_bits(spectra, xi)
     ns = max(_n_spec(bits), 1)
     lm = np.ascontiguousarray(np.asarray(lmax_list, dtype=np.int32))
     n = len(lm)

@@ -580,7 +580,7 @@ size_t batched_workspace_bytes(const BatchPlan& p) {
 }
 
 hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, const int* spec_src, int n_out,
-                          hipStream_t s) {
+                          int xi_only, hipStream_t s) {
     const bool bf16 = precision == COUPLE_MFMA_BF16X3;
     double* xi = reinterpret_cast<double*>(ctx->bws);
     long long xi_off[kMaxGroups][kGroup];
@@ -689,7 +689,7 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
                 j.block0 = 0;
             }
         prof_begin(ctx, s);
-        hipError_t e = launch_fill_jobs(jobs, n_jobs, spec_src, n_out, s);
+        hipError_t e = launch_fill_jobs(jobs, n_jobs, spec_src, n_out, xi_only, s);
         prof_end(ctx, s, 2);
         if (e != hipSuccess) return e;
     }

@@ -107,8 +107,10 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
                  unsigned spectra, int precision, const double* out) {
     if (lmax < 0 || lmax > ctx->lmax_max)
         return fail(ctx, COUPLE_EINVAL, "lmax=%d outside [0, lmax_max=%d]", lmax, ctx->lmax_max);
-    if (spectra == 0 || (spectra & ~0x1Fu))
-        return fail(ctx, COUPLE_EINVAL, "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB|EB",
+    const unsigned spec = spectra & ~(unsigned)COUPLE_XI;
+    if (spec == 0 || (spec & ~0x1Fu))
+        return fail(ctx, COUPLE_EINVAL,
+                    "spectra mask 0x%x: must be a non-empty OR of TT|TE|EE|BB|EB, optionally with COUPLE_XI",
                     spectra);
     if (precision != COUPLE_FP64 && precision != COUPLE_FP32C)
         return fail(ctx, COUPLE_EINVAL,
@@ -259,7 +261,7 @@ int couple_matrix(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     hipError_t e;
     {
         Timed t(ctx, s, 2);
-        e = couple::launch_fill(ctx, lmax, lmax, src, n_out, out, s);
+        e = couple::launch_fill(ctx, lmax, lmax, src, n_out, out, (spectra & COUPLE_XI) ? 1 : 0, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "fill launch");
     return COUPLE_OK;
@@ -317,8 +319,9 @@ int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const do
     if (rc) return rc;
     {
         Timed t(ctx, s, 2);
-        e = binned ? couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, s)
-                   : couple::launch_fill(ctx, lmax, dmax, src, n_out, out, s);
+        const int xi = (spectra & COUPLE_XI) ? 1 : 0;
+        e = binned ? couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, xi, s)
+                   : couple::launch_fill(ctx, lmax, dmax, src, n_out, out, xi, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, binned ? "bin launch" : "fill launch");
     return COUPLE_OK;
@@ -508,7 +511,7 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
     p.tm = ctx->batched_tm[ti];
     int src4[couple::kMaxOut];
     const int n_out = output_sources(spectra, src4);
-    hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, s);
+    hipError_t e = couple::launch_batched(ctx, p, precision, src4, n_out, (spectra & COUPLE_XI) ? 1 : 0, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
     return COUPLE_OK;
 }

@@ -78,13 +78,15 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
 // fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
 //   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE, 3 EB) output i comes from, n_out <= kMaxOut outputs.
 constexpr int kMaxOut = 5;
+//   xi != 0: write Xi itself (no (2 l2 + 1) column factor).
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                       double* out, hipStream_t s);
+                       double* out, int xi, hipStream_t s);
 // Up to kInlineBins bins the edges travel in the kernel arguments (no upload,
 // nothing to synchronise); longer lists are read from bin_edges_dev.
 constexpr int kInlineBins = 512;
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, hipStream_t s);
+                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
+                      hipStream_t s);
 // One fill job: Xi store [3][tri(lmax)] (Xi for diagonals d <= dmax, 0 beyond)
 // and its n_out output matrices [n_out][lmax+1][lmax+1].  block0 is set by
 // launch_fill_jobs.
@@ -96,7 +98,8 @@ struct FillJob {
     int dmax;
     int block0;
 };
-hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, hipStream_t s);
+hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, int xi,
+                            hipStream_t s);
 // out[0 .. n) = 0 with a kernel (safe inside captured graphs)
 hipError_t launch_zero(double* out, size_t n, hipStream_t s);
 
@@ -107,6 +110,6 @@ void prof_end(couple_ctx* ctx, hipStream_t s, int stage);
 // batched form (batched.hip)
 size_t batched_workspace_bytes(const BatchPlan& p);
 hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, const int* spec_src, int n_out,
-                          hipStream_t s);
+                          int xi, hipStream_t s);
 
 }  // namespace couple

@@ -28,6 +28,7 @@ struct FillArgs {
     FillJob job[kMaxFillJobs];
     int n_jobs;
     int n_out;
+    int xi_only;                 // write Xi (column factor 1) instead of K
     int src[kMaxOut];            // Xi index of each output
 };
 
@@ -79,24 +80,26 @@ fill_kernel(FillArgs a) {
             last_src = src;
         }
         double* out = job.out + (long long)o * ld * ld;
+        // column factor fs l + 1: 2 l + 1 for K, 1 for Xi
+        const double fs = a.xi_only ? 0.0 : 2.0;
         if (I == J) {
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int r = idx / kT, c = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
                 if (l1 > lmax || l2 > lmax) continue;
                 const double x = (c >= r) ? tile[r][c] : tile[c][r];
-                __builtin_nontemporal_store((2.0 * l2 + 1.0) * x, &out[l1 * ld + l2]);
+                __builtin_nontemporal_store((fs * l2 + 1.0) * x, &out[l1 * ld + l2]);
             }
         } else {
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int r = idx / kT, c = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((2.0 * l2 + 1.0) * tile[r][c], &out[l1 * ld + l2]);
+                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((fs * l2 + 1.0) * tile[r][c], &out[l1 * ld + l2]);
             }
             for (int idx = t; idx < kT * kT; idx += kFillThreads) {
                 const int c = idx / kT, r = idx % kT;
                 const int l1 = r0 + r, l2 = c0 + c;
-                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((2.0 * l1 + 1.0) * tile[r][c], &out[l2 * ld + l1]);
+                if (l1 <= lmax && l2 <= lmax) __builtin_nontemporal_store((fs * l1 + 1.0) * tile[r][c], &out[l2 * ld + l1]);
             }
         }
     }
@@ -115,6 +118,7 @@ struct BinArgs {
     int lmax;
     int dmax;
     int n_out;
+    int xi_only;                 // bin Xi instead of K
     int src[kMaxOut];
 };
 
@@ -128,6 +132,7 @@ bin_kernel(BinArgs a) {
     const int nr = r_hi - r_lo, ncl = c_hi - c_lo;
     // smallest |l1 - l2| between the two bins
     const int gap = (c_lo >= r_hi) ? c_lo - (r_hi - 1) : (r_lo >= c_hi ? r_lo - (c_hi - 1) : 0);
+    const double fs = a.xi_only ? 0.0 : 2.0;  // column factor fs l2 + 1
     const int t = threadIdx.x;
     for (int o = 0; o < a.n_out; ++o) {
         const double* xi = a.xi + (long long)a.src[o] * a.xi_stride;
@@ -136,7 +141,7 @@ bin_kernel(BinArgs a) {
             for (int idx = t; idx < nr * ncl; idx += kBinThreads) {
                 const int l1 = r_lo + idx / ncl, l2 = c_lo + idx % ncl;
                 const int lo = min(l1, l2), d = abs(l2 - l1);
-                if (d <= a.dmax) acc += (2.0 * l2 + 1.0) * xi[diag_offset(a.lmax, d) + lo];
+                if (d <= a.dmax) acc += (fs * l2 + 1.0) * xi[diag_offset(a.lmax, d) + lo];
             }
         }
         red[t] = acc;
@@ -165,7 +170,8 @@ hipError_t launch_zero(double* out, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, hipStream_t s) {
+hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src, int n_out, int xi,
+                            hipStream_t s) {
     if (n_jobs < 1 || n_jobs > kMaxFillJobs) return hipErrorInvalidValue;
     FillArgs a;
     long long blocks = 0;
@@ -177,24 +183,26 @@ hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src
     }
     a.n_jobs = n_jobs;
     a.n_out = n_out;
+    a.xi_only = xi;
     for (int i = 0; i < kMaxOut; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kFillThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                       double* out, hipStream_t s) {
+                       double* out, int xi, hipStream_t s) {
     FillJob j;
     j.xi = ctx->xi;
     j.out = out;
     j.lmax = lmax;
     j.dmax = dmax;
     j.block0 = 0;
-    return launch_fill_jobs(&j, 1, spec_src, n_out, s);
+    return launch_fill_jobs(&j, 1, spec_src, n_out, xi, s);
 }
 
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, hipStream_t s) {
+                      const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
+                      hipStream_t s) {
     BinArgs a;
     a.xi = ctx->xi;
     a.xi_stride = tri_size(lmax);
@@ -206,6 +214,7 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
     a.lmax = lmax;
     a.dmax = dmax;
     a.n_out = n_out;
+    a.xi_only = xi;
     for (int i = 0; i < kMaxOut; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(n_bins * n_bins)), dim3(kBinThreads), 0, s, a);
     return hipGetLastError();

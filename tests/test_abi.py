@@ -78,3 +78,20 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             couple.load_library(str(tmp_path / "missing.so"))
     finally:
         couple._lib = saved
+
+
+def test_enum_values_match_the_binding():
+    """Spectrum bits, the output-form flag and precisions are the same numbers
+    in the header and in the Python binding."""
+    from paper_2602_15605_amd import couple
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    vals = {k: int(v) for k, v in re.findall(r"\b(COUPLE_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    for name, bit in couple.SPECTRUM_BITS.items():
+        assert vals["COUPLE_" + name] == bit
+    assert vals["COUPLE_XI"] == couple.XI
+    assert couple.XI & 0x1F == 0
+    assert vals["COUPLE_FP64"] == couple.PRECISIONS["fp64"]
+    assert vals["COUPLE_FP32C"] == couple.PRECISIONS["fp32c"]
+    assert vals["COUPLE_MFMA_FP32"] == couple.PRECISIONS["mfma_fp32"]
+    assert vals["COUPLE_MFMA_BF16X3"] == couple.PRECISIONS["mfma_bf16x3"]
