@@ -121,6 +121,27 @@ def run_context(torch, couple, synth):
         "ms": 1e3 * dt, "k_elements_per_s": 4 * (lmax + 1) ** 2 / dt,
         "includes": "couple_init (tables), W host->device, couple_matrix, 1.15 GB K device->host (pageable)"}
     del K, Kh
+    # binned MASTER solve on these windows: bins of 50 from l = 2, TT and the E/B block
+    edges = list(range(2, lmax + 2, 50)) + [lmax + 1]
+    nb = len(edges) - 1
+    Kt = couple.couple_band(ctx, 0, 2 * lmax, dW[0], None, None, lmax, spectra=("TT",), precision="fp32c",
+                            bin_edges=edges)[0].contiguous()
+    Kp = couple.couple_band(ctx, 0, 2 * lmax, None, None, dW[2], lmax, spectra=("EE", "BB", "EB"),
+                            precision="fp32c", bin_edges=edges)
+    cl = torch.ones((3, lmax + 1), dtype=torch.float64, device="cuda")
+    wt = torch.empty(nb * (nb + 1), dtype=torch.float64, device="cuda")
+    wp = torch.empty(2 * nb * (2 * nb + 1), dtype=torch.float64, device="cuda")
+    ctb = torch.empty((3, nb), dtype=torch.float64, device="cuda")
+    xt = torch.empty((1, nb), dtype=torch.float64, device="cuda")
+    xp = torch.empty((1, 2 * nb), dtype=torch.float64, device="cuda")
+    ms_t = _timed(torch, lambda: (couple.couple_bin_spectra(ctx, cl, edges, out=ctb),
+                                  couple.couple_master_solve(ctx, Kt, ctb[0:1], work=wt, out=xt)), 5, 2)
+    ms_p = _timed(torch, lambda: (couple.couple_bin_spectra(ctx, cl, edges, out=ctb),
+                                  couple.couple_master_solve(ctx, Kp, ctb[1:3].reshape(1, -1), work=wp, out=xp)),
+                  5, 2)
+    out["master_solve_lmax6000_bins50"] = {
+        "bins": nb, "tt_ms": ms_t, "eb_block_ms": ms_p,
+        "note": "binned pseudo-spectra + LU solve on one work-group; TT is %d unknowns, E/B %d" % (nb, 2 * nb)}
     couple.couple_free(ctx)
     return out
 

@@ -229,6 +229,44 @@ int couple_autotune_batched(couple_ctx *ctx, int precision, int n_masks, const i
                             int *best_row_tiles, int *best_flush, float *best_ms);
 
 /*
+ * Binned MASTER solve (Sec. 2, eq. pseudo_cl).  The pseudo-spectra are linear
+ * in the true spectra,
+ *   <C~^TT> = K^TT C^TT,
+ *   <C~^EE> = K^EE C^EE + K^EB C^BB,   <C~^BB> = K^EB C^EE + K^BB C^BB
+ * (the B-mode line by the structure of App. A: Xi_BB has the form of Xi_EE and
+ * Xi_BE = Xi_EB).  Binned with the couple_band rule (row-bin average,
+ * column-bin sum, C_l constant inside a bin) this is K_{b b'} C_{b'} = C~_b.
+ *
+ * couple_bin_spectra -- C~_b = (1/n_b) sum_{l in b} C~_l for n_spec spectra.
+ *   cl        : device float64 [n_spec][cl_len].
+ *   bin_edges : HOST array of n_bins+1 strictly increasing multipoles,
+ *               0 <= bin_edges[0], bin_edges[n_bins] <= cl_len,
+ *               1 <= n_bins <= lmax_max+1 (as couple_band).
+ *   out       : device float64 [n_spec][n_bins].
+ *   Up to 512 bins only enqueues a kernel; longer lists synchronise stream
+ *   and stage the edges as couple_band does.
+ *
+ * couple_master_solve -- solve the binned system for n_rhs right-hand sides.
+ *   pol = 0 : K = [n][n] (e.g. binned K^TT); m = n unknowns.
+ *   pol = 1 : K = [3][n][n], the binned K^EE, K^BB, K^EB in that order (the
+ *             output of couple_band with spectra EE|BB|EB); the system is
+ *             [K^EE K^EB; K^EB K^BB] of m = 2n unknowns (C^EE then C^BB).
+ *   rhs  : device float64 [n_rhs][m] (binned pseudo-spectra, EE then BB).
+ *   work : device float64 workspace of m * (m + n_rhs) entries, overwritten.
+ *   x    : device float64 [n_rhs][m], the solution.
+ *   m + n_rhs <= 4096.  Gaussian elimination with partial pivoting in
+ *   float64 on one work-group; K and rhs are not modified.  A singular system
+ *   (a zero pivot column) gives NaN in every entry of x.  Only enqueues one
+ *   kernel (no allocation, graph-capturable).
+ * Errors (both): EINVAL (NULL ctx or pointer, misaligned pointer, sizes or
+ * edges out of range), EDEVICE.
+ */
+int couple_bin_spectra(couple_ctx *ctx, int n_spec, const double *cl, int cl_len, const int *bin_edges,
+                       int n_bins, double *out, void *stream);
+int couple_master_solve(couple_ctx *ctx, int pol, int n, const double *K, int n_rhs, const double *rhs,
+                        double *work, double *x, void *stream);
+
+/*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for
  * inspection and tests).  Any pointer may be NULL to skip that table.
  *   g    : lmax_max + 1 float64,   g[p] = g(p)                  (eq. gdef)

@@ -70,6 +70,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_autotune_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
+    lib.couple_bin_spectra.argtypes = [vp, i, dp, i, vp, i, dp, vp]
+    lib.couple_bin_spectra.restype = i
+    lib.couple_master_solve.argtypes = [vp, i, i, dp, i, dp, dp, dp, vp]
+    lib.couple_master_solve.restype = i
     lib.couple_profile.argtypes = [vp, i]
     lib.couple_profile.restype = i
     lib.couple_profile_read.argtypes = [vp, vp, vp]
@@ -316,6 +320,56 @@ def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE
         ctypes.byref(fl), ctypes.byref(ms))
     _check(rc, ctx)
     return tm.value, fl.value, ms.value
+
+
+def couple_bin_spectra(ctx, cl, bin_edges, out=None, stream=None):
+    """Binned pseudo-spectra C~_b = (1/n_b) sum_{l in b} C~_l (couple_band's row-bin rule).
+
+    ``cl``: float64 GPU tensor [n_spec, cl_len] (or [cl_len]); ``bin_edges`` a host
+    sequence of n_bins+1 increasing multipoles.  Returns [n_spec, n_bins] (or [n_bins]).
+    """
+    import torch
+    one = cl.dim() == 1
+    c2 = cl.reshape(1, -1) if one else cl
+    if not c2.is_contiguous():
+        raise CoupleError(COUPLE_EINVAL, "cl must be contiguous")
+    edges = np.ascontiguousarray(np.asarray(bin_edges, dtype=np.int32))
+    n_bins = len(edges) - 1
+    if out is None:
+        out = torch.empty((c2.shape[0], n_bins), dtype=torch.float64, device=cl.device)
+    rc = load_library().couple_bin_spectra(ctx.handle, int(c2.shape[0]), _dev_ptr(c2, "cl"), int(c2.shape[1]),
+                                           edges.ctypes.data, n_bins, _dev_ptr(out, "out"), _stream_handle(stream))
+    _check(rc, ctx)
+    return out.reshape(-1) if one else out
+
+
+def couple_master_solve(ctx, K, rhs, pol=False, work=None, out=None, stream=None):
+    """Solve the binned MASTER system K_{b b'} C_{b'} = C~_b.
+
+    ``pol=False``: ``K`` is [n, n] (or [1, n, n]); ``rhs`` [n] or [n_rhs, n].
+    ``pol=True``: ``K`` is [3, n, n] = binned (EE, BB, EB) as couple_band writes them
+    for spectra ("EE", "BB", "EB"); ``rhs`` [2n] or [n_rhs, 2n] (EE then BB).
+    Returns the solution with the shape of ``rhs``.
+    """
+    import torch
+    n = int(K.shape[-1])
+    m = 2 * n if pol else n
+    one = rhs.dim() == 1
+    r2 = rhs.reshape(1, -1) if one else rhs
+    if r2.shape[1] != m:
+        raise CoupleError(COUPLE_EINVAL, "rhs has %d entries per system, expected %d" % (r2.shape[1], m))
+    if not (K.is_contiguous() and r2.is_contiguous()):
+        raise CoupleError(COUPLE_EINVAL, "K and rhs must be contiguous")
+    n_rhs = int(r2.shape[0])
+    if work is None:
+        work = torch.empty(m * (m + n_rhs), dtype=torch.float64, device=K.device)
+    if out is None:
+        out = torch.empty((n_rhs, m), dtype=torch.float64, device=K.device)
+    rc = load_library().couple_master_solve(ctx.handle, 1 if pol else 0, n, _dev_ptr(K, "K"), n_rhs,
+                                            _dev_ptr(r2, "rhs"), _dev_ptr(work, "work"), _dev_ptr(out, "x"),
+                                            _stream_handle(stream))
+    _check(rc, ctx)
+    return out.reshape(-1) if one else out
 
 
 def couple_tables(ctx):

@@ -656,3 +656,55 @@ int couple_profile_read(couple_ctx* ctx, double* ms, int* counts) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int couple_bin_spectra(couple_ctx* ctx, int n_spec, const double* cl, int cl_len, const int* bin_edges, int n_bins,
+                       double* out, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (n_spec < 1) return fail(ctx, COUPLE_EINVAL, "n_spec=%d < 1", n_spec);
+    if (!cl || !out) return fail(ctx, COUPLE_EINVAL, "cl or out is NULL");
+    if (reinterpret_cast<uintptr_t>(cl) % alignof(double) || reinterpret_cast<uintptr_t>(out) % alignof(double))
+        return fail(ctx, COUPLE_EINVAL, "cl or out is not 8-byte aligned");
+    if (!bin_edges) return fail(ctx, COUPLE_EINVAL, "bin_edges is NULL");
+    if (n_bins < 1 || n_bins > ctx->lmax_max + 1)
+        return fail(ctx, COUPLE_EINVAL, "n_bins=%d outside [1, lmax_max+1=%d]", n_bins, ctx->lmax_max + 1);
+    if (bin_edges[0] < 0 || bin_edges[n_bins] > cl_len)
+        return fail(ctx, COUPLE_EINVAL, "bin edges must lie in [0, cl_len=%d]", cl_len);
+    for (int b = 0; b < n_bins; ++b)
+        if (bin_edges[b + 1] <= bin_edges[b])
+            return fail(ctx, COUPLE_EINVAL, "bin edges must be strictly increasing (at %d)", b);
+    if ((long long)n_spec * n_bins > 0x7fffffffLL) return fail(ctx, COUPLE_EINVAL, "n_spec * n_bins too large");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_bins > couple::kInlineBins) {
+        int rc = upload_edges(ctx, bin_edges, n_bins, s);
+        if (rc) return rc;
+    }
+    hipError_t e = couple::launch_bin_spectra(ctx, n_spec, cl, cl_len, bin_edges, n_bins, out, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin_spectra launch");
+    return COUPLE_OK;
+}
+
+int couple_master_solve(couple_ctx* ctx, int pol, int n, const double* K, int n_rhs, const double* rhs, double* work,
+                        double* x, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (pol != 0 && pol != 1) return fail(ctx, COUPLE_EINVAL, "pol=%d: 0 (TT) or 1 (E/B block)", pol);
+    if (n < 1 || n_rhs < 1) return fail(ctx, COUPLE_EINVAL, "n=%d and n_rhs=%d must be >= 1", n, n_rhs);
+    const long long m = pol ? 2LL * n : n;
+    if (m + n_rhs > couple::kSolveMaxCols)
+        return fail(ctx, COUPLE_EINVAL, "%lld unknowns + %d right-hand sides exceed %d", m, n_rhs,
+                    couple::kSolveMaxCols);
+    const double* ptrs[] = {K, rhs, work, x};
+    for (const double* p : ptrs) {
+        if (!p) return fail(ctx, COUPLE_EINVAL, "K, rhs, work and x must be non-NULL");
+        if (reinterpret_cast<uintptr_t>(p) % alignof(double))
+            return fail(ctx, COUPLE_EINVAL, "K, rhs, work and x must be 8-byte aligned");
+    }
+    hipError_t e = couple::launch_master_solve(pol, n, K, n_rhs, rhs, work, x, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "master_solve launch");
+    return COUPLE_OK;
+}
+
+}  // extern "C"

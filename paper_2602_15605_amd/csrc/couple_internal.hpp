@@ -103,6 +103,13 @@ hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src
 // out[0 .. n) = 0 with a kernel (safe inside captured graphs)
 hipError_t launch_zero(double* out, size_t n, hipStream_t s);
 
+// binned MASTER solve (solve.hip)
+constexpr int kSolveMaxCols = 4096;    // unknowns + right-hand sides of one solve
+hipError_t launch_bin_spectra(const couple_ctx* ctx, int n_spec, const double* cl, int cl_stride,
+                              const int* bin_edges_host, int n_bins, double* out, hipStream_t s);
+hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const double* rhs, double* work,
+                               double* x, hipStream_t s);
+
 // measurement hook: event marks around a kernel of stage `stage` (no-op unless profiling)
 void prof_begin(couple_ctx* ctx, hipStream_t s);
 void prof_end(couple_ctx* ctx, hipStream_t s, int stage);

@@ -66,6 +66,8 @@ def test_host_side_argument_errors(lib):
     assert lib.couple_band(None, 0, 1, None, None, None, 0, 0, 1, 0, None, 0, None, None) == -1
     assert lib.couple_tables(None, None, None, None, None, None) == -1
     assert lib.couple_lmax_max(None) == -1
+    assert lib.couple_bin_spectra(None, 1, None, 0, None, 1, None, None) == -1
+    assert lib.couple_master_solve(None, 0, 1, None, 1, None, None, None, None) == -1
     lib.couple_free(None)
 
 
