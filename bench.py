@@ -137,7 +137,8 @@ def run_context(torch, couple, synth):
     ms_t = _timed(torch, lambda: (couple.couple_bin_spectra(ctx, cl, edges, out=ctb),
                                   couple.couple_master_solve(ctx, Kt, ctb[0:1], work=wt, out=xt)), 5, 2)
     ms_p = _timed(torch, lambda: (couple.couple_bin_spectra(ctx, cl, edges, out=ctb),
-                                  couple.couple_master_solve(ctx, Kp, ctb[1:3].reshape(1, -1), work=wp, out=xp)),
+                                  couple.couple_master_solve(ctx, Kp, ctb[1:3].reshape(1, -1), pol=True, work=wp,
+                                                              out=xp)),
                   5, 2)
     out["master_solve_lmax6000_bins50"] = {
         "bins": nb, "tt_ms": ms_t, "eb_block_ms": ms_p,

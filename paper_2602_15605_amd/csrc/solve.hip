@@ -10,11 +10,17 @@
 //
 // bin_spectra_kernel: one thread per (spectrum, bin), the bin's sum in l order.
 // master_solve_kernel: one work-group assembles [K | C~] (TT, or the 2 x 2
-// block system for E/B) in the caller's workspace, eliminates with partial
-// pivoting (largest |pivot|, the first row on ties), keeping the pivot row and
-// the multipliers in LDS, and back-substitutes every right-hand side.  The
-// trailing update is row by row per wavefront, 64 consecutive columns per
-// instruction.  A zero pivot (a singular system) gives NaN in every output.
+// block system for E/B) in the caller's workspace and runs a blocked LU with
+// partial pivoting (largest |pivot|, the first row on ties):
+//   * a panel of NB columns (8, or 4 when the rows would not fit) is
+//     factorised in LDS;
+//   * right of the panel, each column applies the panel's row exchanges and
+//     the unit-lower forward substitution U12 = L11^-1 A12;
+//   * the trailing block gets A22 -= L21 U12: lanes over 64 consecutive
+//     columns (U12 in registers), waves over rows (L21 rows broadcast from
+//     LDS), so A is read once per panel instead of once per column.
+// Then every right-hand side (columns m .. of the augmented matrix) is back-
+// substituted.  A zero pivot (a singular system) gives NaN in every output.
 #include "couple_internal.hpp"
 
 namespace couple {
@@ -53,11 +59,30 @@ struct SolveArgs {
     int n, m, n_rhs, pol;
 };
 
+// Largest (|v|, first row on ties) of the candidates of one wave, in lane 0.
+__device__ inline void wave_argmax(double& v, int& idx) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_down(v, off, kWave);
+        const int oi = __shfl_down(idx, off, kWave);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
+
+// Panel of NB columns in LDS: rows k0 .. m-1 (at most kPanelDoubles / NB).
+constexpr int kPanelDoubles = 16384;
+
+template <int NB>
 __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a) {
-    __shared__ double s_row[kSolveMaxCols];      // pivot row
-    __shared__ double s_mul[kSolveMaxCols];      // multipliers of the column
-    __shared__ double s_red[kSolveThreads];
-    __shared__ int s_idx[kSolveThreads];
+    __shared__ double s_panel[kPanelDoubles];    // [row - k0][NB]
+    __shared__ double s_cv[kSolveWaves];         // per-wave pivot candidates
+    __shared__ int s_ci[kSolveWaves];
+    __shared__ double s_pv;                      // chosen pivot magnitude and panel row
+    __shared__ int s_pi;
+    __shared__ int s_perm[NB];                   // row exchanges of the panel (panel rows)
     const int t = threadIdx.x;
     const int lane = t % kWave, wave = t / kWave;
     const int n = a.n, m = a.m, nr = a.n_rhs;
@@ -83,53 +108,109 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
     __syncthreads();
 
     bool singular = false;
-    for (int k = 0; k < m; ++k) {
-        // pivot search over rows k .. m-1 of column k
-        double best = -1.0;
-        int bi = m;
-        for (int i = k + t; i < m; i += kSolveThreads) {
-            const double v = fabs(A[i * ld + k]);
-            if (v > best) {
-                best = v;
-                bi = i;
-            }
+    for (int k0 = 0; k0 < m; k0 += NB) {
+        const int nb = min(NB, m - k0);
+        const int mr = m - k0;
+        // panel: rows k0 .. m-1, columns k0 .. k0+nb-1
+        for (int e = t; e < mr * NB; e += kSolveThreads) {
+            const int r = e / NB, j = e - r * NB;
+            s_panel[e] = j < nb ? A[(k0 + r) * ld + k0 + j] : 0.0;
         }
-        s_red[t] = best;
-        s_idx[t] = bi;
         __syncthreads();
-        for (int w = kSolveThreads / 2; w > 0; w >>= 1) {
-            if (t < w) {
-                const double o = s_red[t + w];
-                const int oi = s_idx[t + w];
-                if (o > s_red[t] || (o == s_red[t] && oi < s_idx[t])) {
-                    s_red[t] = o;
-                    s_idx[t] = oi;
+        for (int j = 0; j < nb; ++j) {
+            double best = -1.0;
+            int bi = mr;
+            for (int r = j + t; r < mr; r += kSolveThreads) {
+                const double v = fabs(s_panel[r * NB + j]);
+                if (v > best) {
+                    best = v;
+                    bi = r;
+                }
+            }
+            wave_argmax(best, bi);
+            if (lane == 0) {
+                s_cv[wave] = best;
+                s_ci[wave] = bi;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double v = lane < kSolveWaves ? s_cv[lane] : -1.0;
+                int idx = lane < kSolveWaves ? s_ci[lane] : mr;
+                wave_argmax(v, idx);
+                if (lane == 0) {
+                    s_pv = v;
+                    s_pi = idx;
                 }
             }
             __syncthreads();
+            const int p = s_pi;
+            if (!(s_pv > 0.0)) {             // zero (or NaN) pivot column: the system is singular
+                singular = true;
+                break;
+            }
+            if (t < NB && p != j) {
+                const double x = s_panel[j * NB + t];
+                s_panel[j * NB + t] = s_panel[p * NB + t];
+                s_panel[p * NB + t] = x;
+            }
+            if (t == 0) s_perm[j] = p;
+            __syncthreads();
+            // multipliers of column j and the rank-1 update of the panel's later columns
+            const double piv = s_panel[j * NB + j];
+            for (int r = j + 1 + t; r < mr; r += kSolveThreads) {
+                const double l = s_panel[r * NB + j] / piv;
+                s_panel[r * NB + j] = l;
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc)
+                    if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
+            }
+            __syncthreads();
         }
-        const int p = s_idx[0];
-        if (!(s_red[0] > 0.0)) {             // zero (or NaN) pivot column: the system is singular
-            singular = true;
-            break;
+        if (singular) break;
+        // U11 back to A; right of the panel: the row exchanges, then U12 = L11^-1 A12
+        for (int e = t; e < nb * nb; e += kSolveThreads) {
+            const int r = e / nb, j = e - r * nb;
+            A[(k0 + r) * ld + k0 + j] = s_panel[r * NB + j];
         }
-        // swap rows k and p from column k on; the pivot row goes to LDS
-        for (int c = k + t; c < (int)ld; c += kSolveThreads) {
-            const double vk = A[k * ld + c], vp = A[p * ld + c];
-            s_row[c] = vp;
-            if (p != k) {
-                A[k * ld + c] = vp;
-                A[p * ld + c] = vk;
+        const int c0 = k0 + nb;
+        for (int c = c0 + t; c < (int)ld; c += kSolveThreads) {
+            for (int j = 0; j < nb; ++j) {
+                const int p = s_perm[j];
+                if (p != j) {
+                    const double x = A[(k0 + j) * ld + c];
+                    A[(k0 + j) * ld + c] = A[(k0 + p) * ld + c];
+                    A[(k0 + p) * ld + c] = x;
+                }
+            }
+            double u[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (j < nb) {
+                    double v = A[(k0 + j) * ld + c];
+#pragma unroll
+                    for (int i = 0; i < NB; ++i)
+                        if (i < j) v = __builtin_fma(-s_panel[j * NB + i], u[i], v);
+                    u[j] = v;
+                    A[(k0 + j) * ld + c] = v;
+                }
             }
         }
         __syncthreads();
-        for (int i = k + 1 + t; i < m; i += kSolveThreads) s_mul[i] = A[i * ld + k] / s_row[k];
-        __syncthreads();
-        // trailing update: rows k+1 .. m-1, columns k+1 .. ld-1
-        for (int i = k + 1 + wave; i < m; i += kSolveWaves) {
-            const double f = s_mul[i];
-            double* Ai = A + i * ld;
-            for (int c = k + 1 + lane; c < (int)ld; c += kWave) Ai[c] = __builtin_fma(-f, s_row[c], Ai[c]);
+        // trailing update A22 -= L21 U12: lanes over 64 consecutive columns, waves over rows
+        for (int cb = c0; cb < (int)ld; cb += kWave) {
+            const int c = cb + lane;
+            const bool live = c < (int)ld;
+            double u[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) u[j] = (live && j < nb) ? A[(k0 + j) * ld + c] : 0.0;
+            for (int i = c0 + wave; i < m; i += kSolveWaves) {
+                if (!live) continue;
+                const double* L = s_panel + (i - k0) * NB;
+                double v = A[i * ld + c];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) v = __builtin_fma(-L[j], u[j], v);
+                A[i * ld + c] = v;
+            }
         }
         __syncthreads();
     }
@@ -185,7 +266,11 @@ hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const
     a.n_rhs = n_rhs;
     a.pol = pol;
     if (a.m + n_rhs > kSolveMaxCols) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(master_solve_kernel, dim3(1), dim3(kSolveThreads), 0, s, a);
+    // the widest panel whose m rows fit in LDS (16 columns would spill registers)
+    if (a.m * 8 <= kPanelDoubles)
+        hipLaunchKernelGGL(master_solve_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(master_solve_kernel<4>, dim3(1), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
 
