@@ -55,7 +55,7 @@ def _load():
 
 
 def threej_row(l1: int, l2: int, m: int) -> np.ndarray:
-    """(l1 l2 l3; m -m 0) for l3 = |l1-l2| .. l1+l2 (m = 0 or -2)."""
+    """(l1 l2 l3; m -m 0) for l3 = |l1-l2| .. l1+l2 (m = 0, -1 or -2)."""
     n = l1 + l2 - abs(l1 - l2) + 1
     out = np.zeros(n, dtype=np.float64)
     rc = _load().oracle_threej_row(int(l1), int(l2), int(m), out.ctypes.data, n)

@@ -30,7 +30,7 @@ def test_rows_equal_racah_small(oracle_bulk):
     worst = 0.0
     for l1 in range(0, 31):
         for l2 in range(0, 31, 1 if l1 < 8 else 3):
-            for m in (0, -2):
+            for m in (0, -1, -2):
                 row = oracle_bulk.threej_row(l1, l2, m)
                 jmin = abs(l1 - l2)
                 exact = np.array([racah.threej(l1, l2, jmin + i, m, -m, 0) for i in range(len(row))])
@@ -40,7 +40,9 @@ def test_rows_equal_racah_small(oracle_bulk):
 
 @pytest.mark.parametrize("l1,l2,l3,m", [(300, 400, 100, -2), (300, 400, 402, -2), (300, 400, 700, 0),
                                         (2, 500, 498, -2), (2, 500, 502, -2), (250, 250, 0, -2),
-                                        (250, 250, 1, -2), (250, 250, 250, -2), (37, 600, 601, -2)])
+                                        (250, 250, 1, -2), (250, 250, 250, -2), (37, 600, 601, -2),
+                                        (300, 400, 101, -1), (300, 400, 650, -1), (1, 500, 500, -1),
+                                        (250, 250, 0, -1), (250, 250, 499, -1)])
 def test_rows_equal_sympy_large(oracle_bulk, l1, l2, l3, m):
     row = oracle_bulk.threej_row(l1, l2, m)
     ref = float(wigner_3j(l1, l2, l3, m, -m, 0))
@@ -73,7 +75,7 @@ def test_rows_000_equal_closed_form_large(oracle_bulk, l1, l2):
 
 
 @pytest.mark.parametrize("l1,l2", [(6000, 6000), (5999, 6000), (2, 6000), (3001, 4444), (1234, 17)])
-@pytest.mark.parametrize("m", [0, -2])
+@pytest.mark.parametrize("m", [0, -1, -2])
 def test_row_ends_equal_single_term_racah(oracle_bulk, l1, l2, m):
     # at l3 = |l1-l2| and l3 = l1+l2 the Racah sum has one term: exact even at l ~ 6000
     row = oracle_bulk.threej_row(l1, l2, m)
@@ -221,3 +223,20 @@ def test_band_rows_equal_restricted_full_rows(oracle_bulk, lmax, lo, hi):
     Kb, Ab = oracle_bulk.coupling_rows(lmax, *Ws, rows=rows, spectra=SPECS, l3_range=(lo, hi), band_forward=True)
     assert np.max(np.abs(Kb - Kf) / (Af + 1e-300)) < 1e-13
     assert np.array_equal(Kf == 0.0, Kb == 0.0)
+
+
+@pytest.mark.parametrize("l1,l2", [(1, 1), (1, 2), (7, 300), (1500, 1500), (6000, 5998), (4000, 6000)])
+def test_row_orthogonality_pins_spin1(oracle_bulk, l1, l2):
+    """(-1 1 0) rows: the even-L half of sum (2l3+1)(-1 1 0)^2 is 1/2 (the even
+    projector is [(-1 1 0) + (1 -1 0)]/2), and the row is orthogonal to the
+    (0 0 0) and (-2 2 0) rows (different m)."""
+    x = oracle_bulk.threej_row(l1, l2, 0)
+    y = oracle_bulk.threej_row(l1, l2, -1)
+    z = oracle_bulk.threej_row(l1, l2, -2)
+    l3 = np.arange(abs(l1 - l2), l1 + l2 + 1)
+    w = 2.0 * l3 + 1.0
+    even = (l1 + l2 + l3) % 2 == 0
+    assert math.fsum(w * y * y) == pytest.approx(1.0, abs=1e-14)
+    assert math.fsum((w * y * y)[even]) == pytest.approx(0.5, abs=1e-14)
+    assert abs(math.fsum(w * x * y)) < 1e-14
+    assert abs(math.fsum(w * y * z)) < 1e-14
