@@ -140,6 +140,19 @@ def run_context(torch, couple, synth):
                                   couple.couple_master_solve(ctx, Kp, ctb[1:3].reshape(1, -1), pol=True, work=wp,
                                                               out=xp)),
                   5, 2)
+    # 3j rows from the tables: 2000 seeded pairs with l1, l2 <= 6000, every l3, each family
+    rng = np.random.default_rng(6001)
+    l1 = rng.integers(0, lmax + 1, 2000).astype(np.int32)
+    l2 = rng.integers(0, lmax + 1, 2000).astype(np.int32)
+    t1, t2 = torch.as_tensor(l1).cuda(), torch.as_tensor(l2).cuda()
+    n_sym = int(np.sum(2 * np.minimum(l1, l2) + 1))
+    rows = torch.empty((2000, 2 * lmax + 1), dtype=torch.float64, device="cuda")
+    for m in (0, 1, 2):
+        ms = _timed(torch, lambda: couple.couple_threej_rows(ctx, t1, t2, m, stride=2 * lmax + 1, out=rows), 5, 2)
+        out["threej_rows_2000pairs_lmax6000_m%d" % m] = {
+            "ms_per_call": ms, "symbols": n_sym, "symbols_per_s": n_sym / (ms * 1e-3),
+            "note": "(l1 l2 l3; -m m 0) for every l3 of each pair, float64, rows padded to 12001"}
+    del rows
     out["master_solve_lmax6000_bins50"] = {
         "bins": nb, "tt_ms": ms_t, "eb_block_ms": ms_p,
         "note": "binned pseudo-spectra + LU solve on one work-group; TT is %d unknowns, E/B %d" % (nb, 2 * nb)}

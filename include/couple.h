@@ -229,6 +229,28 @@ int couple_autotune_batched(couple_ctx *ctx, int precision, int n_masks, const i
                             int *best_row_tiles, int *best_flush, float *best_ms);
 
 /*
+ * couple_threej_rows -- rows of Wigner 3j symbols (l1 l2 l3; -m m 0) for
+ * m = 0, 1, 2 over every l3 = |l1-l2| .. l1+l2, evaluated from the context's
+ * g(p) tables in closed form: the (0 0 0) symbol by eq. 000_sq_main (Sec. 3.1),
+ * the (-1 1 0) family by App. B (eq. joneodd for odd L; eq. joneeven, whose
+ * two terms collapse to one product, for even L) and the (-2 2 0) family by
+ * App. B.3 (eq. 022_linear_closedform, and eq. 022_rearranged for odd L).
+ * These are the symbols of the lensing and aberration weights the paper
+ * names (Sec. 1) as well as of the coupling matrices.  float64.
+ *   m        : 0, 1 or 2.
+ *   l1, l2   : DEVICE int32 arrays of n_pairs multipoles.  A pair outside
+ *              [0, lmax_max] gives a row of NaN (checked on the device).
+ *   out      : device float64 [n_pairs][stride]; out[p][i] is the symbol at
+ *              l3 = |l1-l2| + i for i < 2 min(l1, l2) + 1 and 0 beyond; rows
+ *              longer than stride are cut at stride.
+ * Only enqueues one kernel (no allocation, graph-capturable).
+ * Errors: EINVAL (NULL ctx or pointer, misalignment, m, n_pairs or stride out
+ * of range), EDEVICE.
+ */
+int couple_threej_rows(couple_ctx *ctx, int m, int n_pairs, const int *l1, const int *l2, double *out,
+                       long long stride, void *stream);
+
+/*
  * Binned MASTER solve (Sec. 2, eq. pseudo_cl).  The pseudo-spectra are linear
  * in the true spectra,
  *   <C~^TT> = K^TT C^TT,

@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_autotune_batched.restype = i
     lib.couple_tables.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.couple_tables.restype = i
+    lib.couple_threej_rows.argtypes = [vp, i, i, vp, vp, dp, ctypes.c_longlong, vp]
+    lib.couple_threej_rows.restype = i
     lib.couple_bin_spectra.argtypes = [vp, i, dp, i, vp, i, dp, vp]
     lib.couple_bin_spectra.restype = i
     lib.couple_master_solve.argtypes = [vp, i, i, dp, i, dp, dp, dp, vp]
@@ -320,6 +322,33 @@ def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE
         ctypes.byref(fl), ctypes.byref(ms))
     _check(rc, ctx)
     return tm.value, fl.value, ms.value
+
+
+def couple_threej_rows(ctx, l1, l2, m, stride=None, out=None, stream=None):
+    """Rows of (l1 l2 l3; -m m 0), m = 0, 1, 2, for l3 = |l1-l2| .. l1+l2.
+
+    ``l1``, ``l2``: sequences or int32 GPU tensors of equal length.  Returns a
+    float64 GPU tensor [n_pairs, stride]; row p holds the symbols from
+    l3 = |l1[p]-l2[p]| on, 0 past the row's end.  ``stride`` defaults to the
+    longest row, 2 max(min(l1, l2)) + 1.
+    """
+    import torch
+    dev = torch.device("cuda")
+    t1 = l1 if isinstance(l1, torch.Tensor) else torch.as_tensor(np.asarray(l1, dtype=np.int32))
+    t2 = l2 if isinstance(l2, torch.Tensor) else torch.as_tensor(np.asarray(l2, dtype=np.int32))
+    t1 = t1.to(device=dev, dtype=torch.int32).contiguous()
+    t2 = t2.to(device=dev, dtype=torch.int32).contiguous()
+    if t1.numel() != t2.numel():
+        raise CoupleError(COUPLE_EINVAL, "l1 and l2 differ in length")
+    n = int(t1.numel())
+    if stride is None:
+        stride = 2 * int(torch.minimum(t1, t2).max().item()) + 1 if n else 1
+    if out is None:
+        out = torch.empty((n, int(stride)), dtype=torch.float64, device=dev)
+    rc = load_library().couple_threej_rows(ctx.handle, int(m), n, t1.data_ptr(), t2.data_ptr(), _dev_ptr(out, "out"),
+                                           int(stride), _stream_handle(stream))
+    _check(rc, ctx)
+    return out
 
 
 def couple_bin_spectra(ctx, cl, bin_edges, out=None, stream=None):

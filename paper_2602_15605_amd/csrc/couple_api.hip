@@ -708,3 +708,23 @@ int couple_master_solve(couple_ctx* ctx, int pol, int n, const double* K, int n_
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int couple_threej_rows(couple_ctx* ctx, int m, int n_pairs, const int* l1, const int* l2, double* out,
+                       long long stride, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (m < 0 || m > 2) return fail(ctx, COUPLE_EINVAL, "m=%d: 0, 1 or 2 ((l1 l2 l3; -m m 0))", m);
+    if (n_pairs < 1) return fail(ctx, COUPLE_EINVAL, "n_pairs=%d < 1", n_pairs);
+    if (stride < 1) return fail(ctx, COUPLE_EINVAL, "stride=%lld < 1", stride);
+    if (!l1 || !l2 || !out) return fail(ctx, COUPLE_EINVAL, "l1, l2 and out must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(l1) % alignof(int) || reinterpret_cast<uintptr_t>(l2) % alignof(int) ||
+        reinterpret_cast<uintptr_t>(out) % alignof(double))
+        return fail(ctx, COUPLE_EINVAL, "l1, l2 (4 bytes) or out (8 bytes) misaligned");
+    hipError_t e = couple::launch_threej_rows(ctx, m, n_pairs, l1, l2, out, stride, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "threej_rows launch");
+    return COUPLE_OK;
+}
+
+}  // extern "C"

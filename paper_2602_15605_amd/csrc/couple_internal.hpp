@@ -103,6 +103,10 @@ hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src
 // out[0 .. n) = 0 with a kernel (safe inside captured graphs)
 hipError_t launch_zero(double* out, size_t n, hipStream_t s);
 
+// rows of 3j symbols (l1 l2 l3; -m m 0) from the tables (threej.hip)
+hipError_t launch_threej_rows(const couple_ctx* ctx, int m, int n_pairs, const int* l1, const int* l2, double* out,
+                              long long stride, hipStream_t s);
+
 // binned MASTER solve (solve.hip)
 constexpr int kSolveMaxCols = 4096;    // unknowns + right-hand sides of one solve
 hipError_t launch_bin_spectra(const couple_ctx* ctx, int n_spec, const double* cl, int cl_stride,
