@@ -6,8 +6,12 @@ and raises ``CoupleError`` with the library's message on failure.  If the
 library has not been built, importing the functions works but every call
 raises (there is no fallback path).
 
-Function names follow the C ABI: ``couple_init``, ``couple_matrix``,
-``couple_band``, ``couple_tables``, ``couple_free``, ``couple_last_error``.
+Function names follow the C ABI: ``couple_init``, ``couple_free``,
+``couple_last_error``, ``couple_matrix``, ``couple_band``,
+``couple_band_batched``, ``couple_matrix_batched`` (with ``couple_reserve_batched``,
+the tile setters and ``couple_autotune_batched``), ``couple_bin_spectra``,
+``couple_master_solve``, ``couple_threej_rows``, ``couple_tables`` and the
+profiling hooks.  ``xi=True`` sets the COUPLE_XI output flag.
 """
 import ctypes
 import os
