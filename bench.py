@@ -314,12 +314,16 @@ def main():
         t0 = time.perf_counter()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         ev0.record(stream)
-        for _ in range(args.steps):
+        marks[0].record(stream)
+        for i in range(args.steps):
             couple.couple_matrix(ctx, *dW, lmax, spectra=spectra, precision=prec, out=out, stream=stream)
+            marks[i + 1].record(stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        per_step = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)])
         prof = couple.couple_profile_read(ctx)
         couple.couple_profile(ctx, False)
         ms_step = ev0.elapsed_time(ev1) / args.steps
@@ -328,6 +332,7 @@ def main():
         flops = FLOP_PER_TRIPLE_POL * T
         r = {
             "ms_per_step": ms_step,
+            "ms_per_step_std": float(per_step.std(ddof=1)) if args.steps > 1 else 0.0,
             "wall_ms_per_step": 1e3 * wall / args.steps,
             "k_elements_per_s": n_el / (ms_step * 1e-3),
             "kernel_ms": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
@@ -383,6 +388,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": h["ms_per_step"],
+        "ms_per_step_std": h["ms_per_step_std"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
