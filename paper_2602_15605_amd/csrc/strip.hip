@@ -208,26 +208,56 @@ strip_fp64_kernel(StripArgs a) {
         // stage g(e), e = A - k0 - KC + 1 + slot; h(e), e = A + d + k0 + slot
         const int g_base = A - k0 - KC + 1;
         const int h_base = A + de + k0;
-        for (int slot = lane; slot < W::kLen; slot += kWave) {
+        // the chunk's global loads in two batches (windows, then per-step factors)
+        constexpr int NS = (W::kLen + kWave - 1) / kWave;
+        constexpr int NU = KC / kWave;
+        double gv[NS], hv[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int slot = lane + q * kWave;
             const int eg = g_base + slot, eh = h_base + slot;
-            s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
-            s_h[W::phys(slot)] = (eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
+            gv[q] = (slot < W::kLen && eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
+            hv[q] = (slot < W::kLen && eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
         }
-        for (int s = lane; s < KC; s += kWave) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int slot = lane + q * kWave;
+            if (slot < W::kLen) {
+                s_g[W::phys(slot)] = gv[q];
+                s_h[W::phys(slot)] = hv[q];
+            }
+        }
+        double ga[NU], gb[NU], w0[NU], w1[NU], w2[NU];
+#pragma unroll
+        for (int e = 0; e < NU; ++e) {
+            const int s = lane + e * kWave;
+            ga[e] = gb[e] = w0[e] = w1[e] = w2[e] = 0.0;
+            if (s < kc) {
+                const int k = k0 + s, l3 = de + 2 * k;
+                ga[e] = a.g[k];
+                gb[e] = a.g[de + k];
+                if (EB || POL) w2[e] = wpp[l3];
+                if (!EB) w0[e] = wtt[l3];
+                if (POL) w1[e] = wtp[l3];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NU; ++e) {
+            const int s = lane + e * kWave;
             double4 u = {0.0, 0.0, 0.0, 0.0};
             if (s < kc) {
                 const int k = k0 + s;
                 const int l3 = de + 2 * k;
-                const double gg = a.g[k] * a.g[de + k];
+                const double gg = ga[e] * gb[e];
                 const long long c = (long long)l3 * (l3 + 1);
                 if (EB) {
-                    u.x = wpp[l3] * gg * (double)(c - (long long)d * (d + 1));
+                    u.x = w2[e] * gg * (double)(c - (long long)d * (d + 1));
                     u.w = (double)c;
                 } else {
-                    u.x = wtt[l3] * gg;
+                    u.x = w0[e] * gg;
                     if (POL) {
-                        u.y = wtp[l3] * gg;
-                        u.z = wpp[l3] * gg;
+                        u.y = w1[e] * gg;
+                        u.z = w2[e] * gg;
                         u.w = (double)c;
                     }
                 }
