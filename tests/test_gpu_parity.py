@@ -189,6 +189,25 @@ def test_workload1_sampled_rows(torch_gpu, ctx, oracle_bulk):
         assert np.max(np.abs(xi - xi.T) / scale) < 1e-15
 
 
+@pytest.mark.parametrize("precision,tol,workload", [("fp64", TOL_FP64, 1), ("fp32c", TOL_FP32C, 2)])
+def test_full_matrix_lmax2000(torch_gpu, ctx, oracle_bulk, precision, tol, workload):
+    """Every element of the four 2001 x 2001 matrices against the oracle: the
+    pol4_lmax2000 windows in FP64; the l_c = 1500 windows of the FP32C
+    workload (whose K stays in the float32 range) in FP32C."""
+    import os
+    import time
+    from paper_2602_15605_amd import synth
+    lmax = 2000
+    Ws = synth.workload_windows(workload, lmax=lmax)
+    K = _run(torch_gpu, ctx, Ws, lmax, precision=precision)
+    t0 = time.perf_counter()
+    Kr, Ar = oracle_bulk.coupling_rows(lmax, *Ws, spectra=SPEC4, n_threads=min(16, os.cpu_count() or 1))
+    _say("full lmax 2000 %s: oracle %.1f s" % (precision, time.perf_counter() - t0))
+    for i, s in enumerate(SPEC4):
+        err = assert_parity(K[i], Kr[i], Ar[i], tol, "full lmax 2000 %s %s" % (precision, s))
+        _say("  %s max rel err %.3e" % (s, err))
+
+
 def test_workload2_fp64_sampled_rows(torch_gpu, ctx, oracle_bulk):
     from paper_2602_15605_amd import synth
     lmax = 6000
