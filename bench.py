@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 # fp32 128 lanes/clk/CU (157.3 TFLOP/s), reached on gfx950 by plain (non-packed) fp32 VALU ops.
 PEAK_VALU_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 PEAK_HBM_GBS = 8000.0
-FLOP_PER_TRIPLE_POL = 16  # TT 5 + TE/EE 11
+FLOP_PER_TRIPLE_POL = 16  # TT 5 (X^2: 3 mul, 1 FMA) + TE/EE 11 (N': 2 FMA; 3 mul; 2 FMA accumulations)
 FLOP_PER_TRIPLE_TT = 5
 
 
@@ -268,8 +268,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How it would shard').", file=sys.stderr)
+        print("bench.py runs on one GPU only: the coupling path has no multi-GPU form; every work item is "
+              "independent, so rows would shard by equal work with one gather of K at the end.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -47,7 +47,7 @@ enum couple_status {
     COUPLE_EINVAL = -1,   /* bad argument (detected on the host, nothing enqueued) */
     COUPLE_ENOMEM = -2,   /* device or host allocation failed (couple_init only)   */
     COUPLE_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed            */
-    COUPLE_ENOTSUP = -4   /* valid request this build does not implement           */
+    COUPLE_ENOTSUP = -4   /* valid request the library does not implement          */
 };
 
 /* spectra bit mask; outputs are written in this order */

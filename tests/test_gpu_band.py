@@ -1,6 +1,6 @@
 """Band-limited coupling matrices (Sec. 4.3) at the full band workload:
 lmax = 10000, W_l = 0 above l = 1000, TT/EE/BB, 8 masks in one batched call,
-binned into 200 bins of 50 multipoles (the binning reading of the design doc R11),
+binned into 200 bins of 50 multipoles (bin b = [50 b, 50 b + 50), row-bin average, column-bin sum),
 FP32C.  Checked against the oracle's band tier on seeded bins: rows of a bin
 are evaluated by the oracle and binned by the same rule.
 """
