@@ -204,6 +204,8 @@ def couple_band(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT", "EE", 
     if out is None:
         dev = next(w.device for w in (W_TT, W_TP, W_PP) if w is not None)
         out = torch.empty(shape, dtype=torch.float64, device=dev)
+    elif out.numel() < int(np.prod(shape)):
+        raise CoupleError(COUPLE_EINVAL, "out is too small")
     ws = [W_TT, W_TP, W_PP]
     w_len = min(int(w.numel()) for w in ws if w is not None)
     rc = load_library().couple_band(ctx.handle, int(l3_lo), int(l3_hi), _dev_ptr(W_TT, "W_TT"),
@@ -242,6 +244,8 @@ def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT"
     if out is None:
         dev = next(w[0].device for w in lists if w is not None)
         out = torch.empty(shape, dtype=torch.float64, device=dev)
+    elif out.numel() < int(np.prod(shape)):
+        raise CoupleError(COUPLE_EINVAL, "out is too small")
     arrs = [_ptr_array(w, n)[0] for w, n in zip(lists, ("W_TT", "W_TP", "W_PP"))]
     w_len = min(int(t.numel()) for w in lists if w is not None for t in w)
     rc = load_library().couple_band_batched(
@@ -275,6 +279,8 @@ def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE",
     dev = next(w[0].device for w in lists if w is not None)
     if outs is None:
         outs = [torch.empty((ns, int(L) + 1, int(L) + 1), dtype=torch.float64, device=dev) for L in lm]
+    elif len(outs) != n or any(o.numel() < ns * (int(L) + 1) ** 2 for o, L in zip(outs, lm)):
+        raise CoupleError(COUPLE_EINVAL, "outs must hold one [n_spec, lmax+1, lmax+1] tensor per mask")
     wl = np.ascontiguousarray(np.array([min(int(w[m].numel()) for w in lists if w is not None) for m in range(n)],
                                        dtype=np.int32))
     arrs = [_ptr_array(w, nm)[0] for w, nm in zip(lists, ("W_TT", "W_TP", "W_PP"))]
@@ -315,6 +321,8 @@ def couple_autotune_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE
     dev = next(w[0].device for w in lists if w is not None)
     if outs is None:
         outs = [torch.empty((ns, int(L) + 1, int(L) + 1), dtype=torch.float64, device=dev) for L in lm]
+    elif len(outs) != n or any(o.numel() < ns * (int(L) + 1) ** 2 for o, L in zip(outs, lm)):
+        raise CoupleError(COUPLE_EINVAL, "outs must hold one [n_spec, lmax+1, lmax+1] tensor per mask")
     wl = np.ascontiguousarray(np.array([min(int(w[m].numel()) for w in lists if w is not None) for m in range(n)],
                                        dtype=np.int32))
     arrs = [_ptr_array(w, nm)[0] for w, nm in zip(lists, ("W_TT", "W_TP", "W_PP"))]
@@ -349,6 +357,8 @@ def couple_threej_rows(ctx, l1, l2, m, stride=None, out=None, stream=None):
         stride = 2 * int(torch.minimum(t1, t2).max().item()) + 1 if n else 1
     if out is None:
         out = torch.empty((n, int(stride)), dtype=torch.float64, device=dev)
+    elif out.numel() < n * int(stride):
+        raise CoupleError(COUPLE_EINVAL, "out holds %d entries, needs %d" % (out.numel(), n * int(stride)))
     rc = load_library().couple_threej_rows(ctx.handle, int(m), n, t1.data_ptr(), t2.data_ptr(), _dev_ptr(out, "out"),
                                            int(stride), _stream_handle(stream))
     _check(rc, ctx)
@@ -370,6 +380,8 @@ def couple_bin_spectra(ctx, cl, bin_edges, out=None, stream=None):
     n_bins = len(edges) - 1
     if out is None:
         out = torch.empty((c2.shape[0], n_bins), dtype=torch.float64, device=cl.device)
+    elif out.numel() < c2.shape[0] * n_bins:
+        raise CoupleError(COUPLE_EINVAL, "out holds %d entries, needs %d" % (out.numel(), c2.shape[0] * n_bins))
     rc = load_library().couple_bin_spectra(ctx.handle, int(c2.shape[0]), _dev_ptr(c2, "cl"), int(c2.shape[1]),
                                            edges.ctypes.data, n_bins, _dev_ptr(out, "out"), _stream_handle(stream))
     _check(rc, ctx)
@@ -394,10 +406,16 @@ def couple_master_solve(ctx, K, rhs, pol=False, work=None, out=None, stream=None
     if not (K.is_contiguous() and r2.is_contiguous()):
         raise CoupleError(COUPLE_EINVAL, "K and rhs must be contiguous")
     n_rhs = int(r2.shape[0])
+    if K.numel() < (3 if pol else 1) * n * n:
+        raise CoupleError(COUPLE_EINVAL, "K holds %d entries, expected %d" % (K.numel(), (3 if pol else 1) * n * n))
     if work is None:
         work = torch.empty(m * (m + n_rhs), dtype=torch.float64, device=K.device)
+    elif work.numel() < m * (m + n_rhs):
+        raise CoupleError(COUPLE_EINVAL, "work holds %d entries, needs %d" % (work.numel(), m * (m + n_rhs)))
     if out is None:
         out = torch.empty((n_rhs, m), dtype=torch.float64, device=K.device)
+    elif out.numel() < n_rhs * m:
+        raise CoupleError(COUPLE_EINVAL, "out holds %d entries, needs %d" % (out.numel(), n_rhs * m))
     rc = load_library().couple_master_solve(ctx.handle, 1 if pol else 0, n, _dev_ptr(K, "K"), n_rhs,
                                             _dev_ptr(r2, "rhs"), _dev_ptr(work, "work"), _dev_ptr(out, "x"),
                                             _stream_handle(stream))

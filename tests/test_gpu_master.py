@@ -254,3 +254,27 @@ def test_graph_replay(torch_gpu, ctx):
         assert torch.equal(x, eager), rep
         del y
     del graph
+
+
+def test_binding_rejects_small_buffers(torch_gpu, ctx):
+    """The C ABI cannot see the size of a caller's device buffer; the binding
+    checks work and out before any launch."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    K = _gpu(torch, np.eye(10))
+    b = _gpu(torch, np.ones(10))
+    with pytest.raises(couple.CoupleError, match="work"):
+        couple.couple_master_solve(ctx, K, b, work=torch.empty(50, dtype=torch.float64, device="cuda"))
+    with pytest.raises(couple.CoupleError, match="out"):
+        couple.couple_master_solve(ctx, K, b, out=torch.empty(5, dtype=torch.float64, device="cuda"))
+    with pytest.raises(couple.CoupleError, match="expected"):
+        couple.couple_master_solve(ctx, K, _gpu(torch, np.ones(20)), pol=True)
+    with pytest.raises(couple.CoupleError, match="out"):
+        couple.couple_bin_spectra(ctx, _gpu(torch, np.ones((2, 30))), [0, 10, 30],
+                                  out=torch.empty(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(couple.CoupleError, match="out"):
+        couple.couple_threej_rows(ctx, [5, 6], [5, 6], 0, stride=13,
+                                  out=torch.empty(20, dtype=torch.float64, device="cuda"))
+    with pytest.raises(couple.CoupleError, match="too small"):
+        couple.couple_band(ctx, 0, 20, b, None, None, 9, spectra=("TT",),
+                           out=torch.empty(50, dtype=torch.float64, device="cuda"))
