@@ -14,8 +14,9 @@
 // are non-temporal.  K^BB is written from the same LDS values as K^EE.  Xi_EB is
 // symmetric as well (the (-2 2 0)^2 of odd L is even under l1 <-> l2).
 //
-// bin: K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2} per
-// (b, b') work-group, reduced in a fixed order.
+// bin: K_{b b'} = (1/n_b) sum_{l1 in b} sum_{l2 in b'} K_{l1 l2}; one
+// work-group per unordered bin pair reads its Xi elements once and writes
+// both K_{b b'} and K_{b' b}, reduced in a fixed order.
 #include "couple_internal.hpp"
 
 namespace couple {
@@ -106,6 +107,8 @@ fill_kernel(FillArgs a) {
 }
 
 constexpr int kBinThreads = 256;
+constexpr int kBinWaves = kBinThreads / kWave;
+constexpr int kBinUnroll = 4;    // diagonals per wave with their loads in flight together
 
 struct BinArgs {
     const double* xi;
@@ -119,40 +122,107 @@ struct BinArgs {
     int dmax;
     int n_out;
     int xi_only;                 // bin Xi instead of K
-    int src[kMaxOut];
+    int n_src;                   // distinct Xi stores among the outputs
+    int src[kMaxOut];            // Xi index of each distinct store
+    int slot[kMaxOut];           // which distinct store output i reads
 };
 
+// One work-group per bin pair bb <= bc (the blocks with bb > bc return at
+// once).  Xi(l1, l2) = Xi(l2, l1), so every element of the pair is read once,
+// from the upper triangle (d = l2 - l1 >= 0, lanes over consecutive l1 of one
+// diagonal: contiguous in the packed store), and feeds both outputs:
+//   out[bb][bc] = (1/n_bb) sum (fs l2 + 1) Xi(l1, l2),
+//   out[bc][bb] = (1/n_bc) sum (fs l1 + 1) Xi(l1, l2);
+// in a diagonal pair both sums land in out[bb][bb], the d = 0 elements once.
+// Outputs that share a Xi store (K^EE and K^BB) share its sums.  Each lane
+// sums its own elements in a fixed order, then the waves and the work-group
+// reduce in a fixed order, so the result does not depend on timing.  A pair
+// outside the band writes its two zeros and returns.  NS = the number of
+// distinct stores, so that only their sums take registers.
+template <int NS>
 __global__ void __launch_bounds__(kBinThreads)
 bin_kernel(BinArgs a) {
-    __shared__ double red[kBinThreads];
+    __shared__ double red[kBinWaves][2 * NS];
     const int bb = blockIdx.x / a.n_bins, bc = blockIdx.x % a.n_bins;
+    if (bb > bc) return;
     const int* E = a.inline_edges ? a.edges_in : a.edges;
     const int r_lo = E[bb], r_hi = E[bb + 1];
     const int c_lo = E[bc], c_hi = E[bc + 1];
-    const int nr = r_hi - r_lo, ncl = c_hi - c_lo;
-    // smallest |l1 - l2| between the two bins
-    const int gap = (c_lo >= r_hi) ? c_lo - (r_hi - 1) : (r_lo >= c_hi ? r_lo - (c_hi - 1) : 0);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const double fs = a.xi_only ? 0.0 : 2.0;  // column factor fs l2 + 1
-    const int t = threadIdx.x;
-    for (int o = 0; o < a.n_out; ++o) {
-        const double* xi = a.xi + (long long)a.src[o] * a.xi_stride;
-        double acc = 0.0;
-        if (gap <= a.dmax) {
-            for (int idx = t; idx < nr * ncl; idx += kBinThreads) {
-                const int l1 = r_lo + idx / ncl, l2 = c_lo + idx % ncl;
-                const int lo = min(l1, l2), d = abs(l2 - l1);
-                if (d <= a.dmax) acc += (fs * l2 + 1.0) * xi[diag_offset(a.lmax, d) + lo];
+    // d = l2 - l1 over the pair (the bins are ordered and disjoint: d >= 1 off the diagonal)
+    const int d_lo = max(c_lo - (r_hi - 1), 0);
+    const int d_hi = min(c_hi - 1 - r_lo, a.dmax);
+    if (d_lo > d_hi) {
+        const int o = threadIdx.x;
+        if (o < a.n_out) {
+            double* out = a.out + (long long)o * a.n_bins * a.n_bins;
+            out[(long long)bb * a.n_bins + bc] = 0.0;
+            out[(long long)bc * a.n_bins + bb] = 0.0;
+        }
+        return;
+    }
+    double sa[NS], sb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) sa[s] = sb[s] = 0.0;
+    for (int l1c = r_lo; l1c < r_hi; l1c += kWave) {
+        // the diagonals that meet rows l1c .. l1c + 63 of this row bin inside the column bin
+        const int row_end = min(l1c + kWave, r_hi);
+        const int dk_lo = max(d_lo, c_lo - (row_end - 1)), dk_hi = min(d_hi, c_hi - 1 - l1c);
+        const int l1 = l1c + lane;
+        for (int d0 = dk_lo + wave; d0 <= dk_hi; d0 += kBinWaves * kBinUnroll) {
+            double x[kBinUnroll][NS], wa[kBinUnroll], wb[kBinUnroll];
+#pragma unroll
+            for (int u = 0; u < kBinUnroll; ++u) {
+                const int d = d0 + u * kBinWaves, l2 = l1 + d;
+                const bool ok = d <= dk_hi && l1 < row_end && l2 >= c_lo && l2 < c_hi;
+                wa[u] = ok ? fs * l2 + 1.0 : 0.0;
+                wb[u] = (ok && d > 0) ? fs * l1 + 1.0 : 0.0;
+                const long long off = ok ? diag_offset(a.lmax, d) + l1 : 0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) x[u][s] = ok ? a.xi[(long long)a.src[s] * a.xi_stride + off] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBinUnroll; ++u) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    sa[s] = __builtin_fma(wa[u], x[u][s], sa[s]);
+                    sb[s] = __builtin_fma(wb[u], x[u][s], sb[s]);
+                }
             }
         }
-        red[t] = acc;
-        __syncthreads();
-        for (int w = kBinThreads / 2; w > 0; w >>= 1) {
-            if (t < w) red[t] += red[t + w];
-            __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            sa[s] += __shfl_down(sa[s], off, kWave);
+            sb[s] += __shfl_down(sb[s], off, kWave);
         }
-        if (t == 0)
-            a.out[((long long)o * a.n_bins + bb) * a.n_bins + bc] = red[0] / (double)nr;
-        __syncthreads();
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            red[wave][2 * s] = sa[s];
+            red[wave][2 * s + 1] = sb[s];
+        }
+    }
+    __syncthreads();
+    const int o = threadIdx.x;
+    if (o < a.n_out) {
+        const int s = a.slot[o];
+        double A = 0.0, B = 0.0;
+        for (int w = 0; w < kBinWaves; ++w) {
+            A += red[w][2 * s];
+            B += red[w][2 * s + 1];
+        }
+        double* out = a.out + (long long)o * a.n_bins * a.n_bins;
+        if (bb == bc) {
+            out[(long long)bb * a.n_bins + bb] = (A + B) / (double)(r_hi - r_lo);
+        } else {
+            out[(long long)bb * a.n_bins + bc] = A / (double)(r_hi - r_lo);
+            out[(long long)bc * a.n_bins + bb] = B / (double)(c_hi - c_lo);
+        }
     }
 }
 
@@ -215,8 +285,22 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
     a.dmax = dmax;
     a.n_out = n_out;
     a.xi_only = xi;
-    for (int i = 0; i < kMaxOut; ++i) a.src[i] = i < n_out ? spec_src[i] : 0;
-    hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(n_bins * n_bins)), dim3(kBinThreads), 0, s, a);
+    // distinct Xi stores, in order of first use
+    a.n_src = 0;
+    for (int i = 0; i < kMaxOut; ++i) a.src[i] = a.slot[i] = 0;
+    for (int i = 0; i < n_out; ++i) {
+        int k = 0;
+        while (k < a.n_src && a.src[k] != spec_src[i]) ++k;
+        if (k == a.n_src) a.src[a.n_src++] = spec_src[i];
+        a.slot[i] = k;
+    }
+    const dim3 grid((unsigned)(n_bins * n_bins)), block(kBinThreads);
+    switch (a.n_src) {
+    case 1: hipLaunchKernelGGL(bin_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(bin_kernel<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(bin_kernel<3>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(bin_kernel<4>, grid, block, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
