@@ -13,14 +13,18 @@
 // block system for E/B) in the caller's workspace and runs a blocked LU with
 // partial pivoting (largest |pivot|, the first row on ties):
 //   * a panel of NB columns (8, or 4 when the rows would not fit) is
-//     factorised in LDS;
+//     factorised in LDS by one wave, with no work-group barrier per column;
 //   * right of the panel, each column applies the panel's row exchanges and
 //     the unit-lower forward substitution U12 = L11^-1 A12;
 //   * the trailing block gets A22 -= L21 U12: lanes over 64 consecutive
-//     columns (U12 in registers), waves over rows (L21 rows broadcast from
-//     LDS), so A is read once per panel instead of once per column.
-// Then every right-hand side (columns m .. of the augmented matrix) is back-
-// substituted.  A zero pivot (a singular system) gives NaN in every output.
+//     columns (U12 in registers), the waves split over (column chunk, row
+//     group) tasks, and each lane loads 8 rows before it stores any, so A is
+//     read once per panel with several loads in flight.
+// Then the right-hand sides (columns m .. of the augmented matrix) are back-
+// substituted in blocks of kBackBlock rows from the bottom, a chunk of them
+// held in LDS: one wave per right-hand side solves the diagonal block (lanes
+// over its rows), then every thread updates rows above from U read straight
+// from memory.  A zero pivot (a singular system) gives NaN in every output.
 #include "couple_internal.hpp"
 
 namespace couple {
@@ -59,6 +63,14 @@ struct SolveArgs {
     int n, m, n_rhs, pol;
 };
 
+// The value lane 0 holds, in every lane.
+__device__ inline double lane0_double(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Largest (|v|, first row on ties) of the candidates of one wave, in lane 0.
 __device__ inline void wave_argmax(double& v, int& idx) {
 #pragma unroll
@@ -74,15 +86,19 @@ __device__ inline void wave_argmax(double& v, int& idx) {
 
 // Panel of NB columns in LDS: rows k0 .. m-1 (at most kPanelDoubles / NB).
 constexpr int kPanelDoubles = 16384;
+constexpr int kRowBatch = 8;      // rows of the trailing update loaded before any is stored
+constexpr int kWavePanelRows = 512;  // panels up to this many rows are factorised by one wave
+constexpr int kBackBlock = 64;    // rows per diagonal block of the back substitution
 
 template <int NB>
 __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a) {
     __shared__ double s_panel[kPanelDoubles];    // [row - k0][NB]
-    __shared__ double s_cv[kSolveWaves];         // per-wave pivot candidates
+    __shared__ int s_perm[NB];                   // row exchanges of the panel (panel rows)
+    __shared__ int s_sing;                       // the panel met a zero pivot
+    __shared__ double s_cv[kSolveWaves];         // per-wave pivot candidates (tall panels)
     __shared__ int s_ci[kSolveWaves];
     __shared__ double s_pv;                      // chosen pivot magnitude and panel row
     __shared__ int s_pi;
-    __shared__ int s_perm[NB];                   // row exchanges of the panel (panel rows)
     const int t = threadIdx.x;
     const int lane = t % kWave, wave = t / kWave;
     const int n = a.n, m = a.m, nr = a.n_rhs;
@@ -117,54 +133,103 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
             s_panel[e] = j < nb ? A[(k0 + r) * ld + k0 + j] : 0.0;
         }
         __syncthreads();
-        for (int j = 0; j < nb; ++j) {
-            double best = -1.0;
-            int bi = mr;
-            for (int r = j + t; r < mr; r += kSolveThreads) {
-                const double v = fabs(s_panel[r * NB + j]);
-                if (v > best) {
-                    best = v;
-                    bi = r;
-                }
-            }
-            wave_argmax(best, bi);
-            if (lane == 0) {
-                s_cv[wave] = best;
-                s_ci[wave] = bi;
-            }
-            __syncthreads();
+        if (mr <= kWavePanelRows) {
+            // short panel: one wave, no work-group barrier per column
             if (wave == 0) {
-                double v = lane < kSolveWaves ? s_cv[lane] : -1.0;
-                int idx = lane < kSolveWaves ? s_ci[lane] : mr;
-                wave_argmax(v, idx);
-                if (lane == 0) {
-                    s_pv = v;
-                    s_pi = idx;
-                }
-            }
-            __syncthreads();
-            const int p = s_pi;
-            if (!(s_pv > 0.0)) {             // zero (or NaN) pivot column: the system is singular
-                singular = true;
-                break;
-            }
-            if (t < NB && p != j) {
-                const double x = s_panel[j * NB + t];
-                s_panel[j * NB + t] = s_panel[p * NB + t];
-                s_panel[p * NB + t] = x;
-            }
-            if (t == 0) s_perm[j] = p;
-            __syncthreads();
-            // multipliers of column j and the rank-1 update of the panel's later columns
-            const double piv = s_panel[j * NB + j];
-            for (int r = j + 1 + t; r < mr; r += kSolveThreads) {
-                const double l = s_panel[r * NB + j] / piv;
-                s_panel[r * NB + j] = l;
+                bool sing = false;
+                for (int j = 0; j < nb; ++j) {
+                    double best = -1.0;
+                    int bi = mr;
+                    for (int r = j + lane; r < mr; r += kWave) {
+                        const double v = fabs(s_panel[r * NB + j]);
+                        if (v > best) {
+                            best = v;
+                            bi = r;
+                        }
+                    }
+                    wave_argmax(best, bi);
+                    best = lane0_double(best);
+                    bi = __builtin_amdgcn_readfirstlane(bi);
+                    if (!(best > 0.0)) {         // zero (or NaN) pivot column: the system is singular
+                        sing = true;
+                        break;
+                    }
+                    if (lane < NB && bi != j) {
+                        const double x = s_panel[j * NB + lane];
+                        s_panel[j * NB + lane] = s_panel[bi * NB + lane];
+                        s_panel[bi * NB + lane] = x;
+                    }
+                    if (lane == 0) s_perm[j] = bi;
+                    // the exchanged rows are read by other lanes of this wave
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    // multipliers of column j and the rank-1 update of the panel's later columns
+                    const double piv = s_panel[j * NB + j];
+                    for (int r = j + 1 + lane; r < mr; r += kWave) {
+                        const double l = s_panel[r * NB + j] / piv;
+                        s_panel[r * NB + j] = l;
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc)
-                    if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
+                        for (int cc = 0; cc < NB; ++cc)
+                            if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (lane == 0) s_sing = sing ? 1 : 0;
             }
             __syncthreads();
+            singular = s_sing != 0;
+        } else {
+            // tall panel: every wave scans rows; four work-group barriers per column
+            for (int j = 0; j < nb; ++j) {
+                double best = -1.0;
+                int bi = mr;
+                for (int r = j + t; r < mr; r += kSolveThreads) {
+                    const double v = fabs(s_panel[r * NB + j]);
+                    if (v > best) {
+                        best = v;
+                        bi = r;
+                    }
+                }
+                wave_argmax(best, bi);
+                if (lane == 0) {
+                    s_cv[wave] = best;
+                    s_ci[wave] = bi;
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    double v = lane < kSolveWaves ? s_cv[lane] : -1.0;
+                    int idx = lane < kSolveWaves ? s_ci[lane] : mr;
+                    wave_argmax(v, idx);
+                    if (lane == 0) {
+                        s_pv = v;
+                        s_pi = idx;
+                    }
+                }
+                __syncthreads();
+                const int p = s_pi;
+                if (!(s_pv > 0.0)) {             // zero (or NaN) pivot column: the system is singular
+                    singular = true;
+                    break;
+                }
+                if (t < NB && p != j) {
+                    const double x = s_panel[j * NB + t];
+                    s_panel[j * NB + t] = s_panel[p * NB + t];
+                    s_panel[p * NB + t] = x;
+                }
+                if (t == 0) s_perm[j] = p;
+                __syncthreads();
+                // multipliers of column j and the rank-1 update of the panel's later columns
+                const double piv = s_panel[j * NB + j];
+                for (int r = j + 1 + t; r < mr; r += kSolveThreads) {
+                    const double l = s_panel[r * NB + j] / piv;
+                    s_panel[r * NB + j] = l;
+#pragma unroll
+                    for (int cc = 0; cc < NB; ++cc)
+                        if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
+                }
+                __syncthreads();
+            }
         }
         if (singular) break;
         // U11 back to A; right of the panel: the row exchanges, then U12 = L11^-1 A12
@@ -196,20 +261,32 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
             }
         }
         __syncthreads();
-        // trailing update A22 -= L21 U12: lanes over 64 consecutive columns, waves over rows
-        for (int cb = c0; cb < (int)ld; cb += kWave) {
-            const int c = cb + lane;
+        // trailing update A22 -= L21 U12: lanes over 64 consecutive columns; the
+        // waves take (column chunk, row group) tasks
+        const int nchunk = ((int)ld - c0 + kWave - 1) / kWave;
+        const int groups = max(1, kSolveWaves / nchunk);
+        for (int task = wave; task < nchunk * groups; task += kSolveWaves) {
+            const int chunk = task % nchunk, grp = task / nchunk;
+            const int c = c0 + chunk * kWave + lane;
             const bool live = c < (int)ld;
             double u[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) u[j] = (live && j < nb) ? A[(k0 + j) * ld + c] : 0.0;
-            for (int i = c0 + wave; i < m; i += kSolveWaves) {
-                if (!live) continue;
-                const double* L = s_panel + (i - k0) * NB;
-                double v = A[i * ld + c];
+            for (int i0 = c0 + grp * kRowBatch; i0 < m; i0 += groups * kRowBatch) {
+                double v[kRowBatch];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) v = __builtin_fma(-L[j], u[j], v);
-                A[i * ld + c] = v;
+                for (int q = 0; q < kRowBatch; ++q) v[q] = (live && i0 + q < m) ? A[(i0 + q) * ld + c] : 0.0;
+#pragma unroll
+                for (int q = 0; q < kRowBatch; ++q) {
+                    if (i0 + q < m) {
+                        const double* L = s_panel + (i0 + q - k0) * NB;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) v[q] = __builtin_fma(-L[j], u[j], v[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kRowBatch; ++q)
+                    if (live && i0 + q < m) A[(i0 + q) * ld + c] = v[q];
             }
         }
         __syncthreads();
@@ -219,20 +296,51 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
         for (long long e = t; e < (long long)nr * m; e += kSolveThreads) a.x[e] = __builtin_nan("");
         return;
     }
-    // back substitution, every right-hand side at once (columns m .. ld-1 of A)
-    for (int i = m - 1; i >= 0; --i) {
-        const double u = A[i * ld + i];
-        for (int r = t; r < nr; r += kSolveThreads) A[i * ld + m + r] /= u;
+    // back substitution in blocks of kBackBlock rows from the bottom; a chunk
+    // of rc right-hand sides is held in LDS (the panel buffer, free now)
+    double* Ub = s_panel;                                    // [kBackBlock][kBackBlock + 1]
+    double* Xs = s_panel + kBackBlock * (kBackBlock + 1);    // [m][rc]
+    const int rc_max = (kPanelDoubles - kBackBlock * (kBackBlock + 1)) / m;
+    for (int r0 = 0; r0 < nr; r0 += rc_max) {
+        const int rc = min(rc_max, nr - r0);
         __syncthreads();
-        for (int q = wave; q < i; q += kSolveWaves) {
-            const double f = A[q * ld + i];
-            for (int r = lane; r < nr; r += kWave) A[q * ld + m + r] = __builtin_fma(-f, A[i * ld + m + r], A[q * ld + m + r]);
+        for (int e = t; e < m * rc; e += kSolveThreads) {
+            const int q = e / rc, c = e - q * rc;
+            Xs[e] = A[q * ld + m + r0 + c];
         }
-        __syncthreads();
-    }
-    for (long long e = t; e < (long long)nr * m; e += kSolveThreads) {
-        const int r = (int)(e / m), i = (int)(e - (long long)r * m);
-        a.x[e] = A[i * ld + m + r];
+        for (int ie = m; ie > 0; ie -= kBackBlock) {
+            const int ib = max(0, ie - kBackBlock), bs = ie - ib;
+            for (int e = t; e < bs * bs; e += kSolveThreads) {
+                const int r = e / bs, c = e - r * bs;
+                Ub[r * (kBackBlock + 1) + c] = A[(ib + r) * ld + ib + c];
+            }
+            __syncthreads();
+            // diagonal block: one wave per right-hand side, lanes over its rows
+            for (int c = wave; c < rc; c += kSolveWaves) {
+                double xv = lane < bs ? Xs[(ib + lane) * rc + c] : 0.0;
+                for (int i = bs - 1; i >= 0; --i) {
+                    const double xi = __shfl(xv, i, kWave) / Ub[i * (kBackBlock + 1) + i];
+                    if (lane == i) xv = xi;
+                    else if (lane < i) xv = __builtin_fma(-Ub[lane * (kBackBlock + 1) + i], xi, xv);
+                }
+                if (lane < bs) Xs[(ib + lane) * rc + c] = xv;
+            }
+            __syncthreads();
+            // rows above the block: X[q] -= U[q][ib .. ie) X[ib .. ie)
+            for (int e = t; e < ib * rc; e += kSolveThreads) {
+                const int q = e / rc, c = e - q * rc;
+                const double* Uq = A + (long long)q * ld + ib;
+                double acc = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < bs; ++j) acc = __builtin_fma(Uq[j], Xs[(ib + j) * rc + c], acc);
+                Xs[e] -= acc;
+            }
+            __syncthreads();
+        }
+        for (long long e = t; e < (long long)rc * m; e += kSolveThreads) {
+            const int c = (int)(e / m), i = (int)(e - (long long)c * m);
+            a.x[(long long)(r0 + c) * m + i] = Xs[i * rc + c];
+        }
     }
 }
 
