@@ -29,6 +29,7 @@ namespace couple {
 namespace {
 
 constexpr int kThreejThreads = 256;
+constexpr int kThreejBatch = 4;
 
 struct ThreejArgs {
     const double* g;             // g(p), p = 0 .. lmax_max
@@ -53,29 +54,35 @@ __device__ inline double x000(const ThreejArgs& a, long long j1, long long j2, l
     return (P & 1) ? -v : v;
 }
 
+// Both parities share one (0 0 0) evaluation: (l1 l2 l3) for even L and
+// (l1, l2+1, l3) for odd L, whose total is then even.  Neighbouring l3
+// alternate in parity, so the two factors are both formed and one is selected
+// per lane, which keeps the wave on a single path.  For m = 1, 2 the factor of
+// the parity not taken can be the root of a negative number; it is discarded.
 __device__ inline double symbol(const ThreejArgs& a, long long l1, long long l2, long long l3) {
     const long long L = l1 + l2 + l3;
-    const bool odd = (L & 1) != 0;
     if (a.m == 0) return x000(a, l1, l2, l3);
+    const long long odd = L & 1;
+    const double x = x000(a, l1, l2 + odd, l3);
     const long long A = l1 * (l1 + 1), B = l2 * (l2 + 1), C = l3 * (l3 + 1);
     if (a.m == 1) {
         if (l1 < 1 || l2 < 1) return 0.0;
-        if (!odd) return -x000(a, l1, l2, l3) * (double)(A + B - C) / (2.0 * sqrt((double)A) * sqrt((double)B));
         const double num = (double)((L + 2) * (L - 2 * l3 + 1)) * (double)((L - 2 * l1 + 1) * (L - 2 * l2));
-        return -0.5 * sqrt(num / ((double)A * (double)B)) * x000(a, l1, l2 + 1, l3);
+        const double f = odd ? sqrt(num) : (double)(A + B - C);
+        return -0.5 * f / sqrt((double)A * (double)B) * x;
     }
     if (l1 < 2 || l2 < 2) return 0.0;
     const double s = 0.5 * a.cl[l1] * a.cl[l2];
-    if (!odd) {
-        const long long np = C * (C - 2 * (A + B - 1)) + A * (A - 2) + B * (B - 2);
-        return x000(a, l1, l2, l3) * (double)np * s;
-    }
+    const long long np = C * (C - 2 * (A + B - 1)) + A * (A - 2) + B * (B - 2);
     const long long sg = l1 + l2 + 1, tau = sg + 1, d = l2 - l1;
     const long long mu = 2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1);
     const long long f1 = sg * (sg + 1) - C, f2 = C - d * (d + 1);
-    return -x000(a, l1, l2 + 1, l3) * (double)(C + mu) * s * sqrt((double)f1 * (double)f2);
+    const double f = odd ? -(double)(C + mu) * sqrt((double)f1 * (double)f2) : (double)np;
+    return x * f * s;
 }
 
+// Each thread computes kThreejBatch symbols of its row before it stores any,
+// so their table reads are in flight together.
 __global__ void __launch_bounds__(kThreejThreads) threej_rows_kernel(ThreejArgs a) {
     const long long p = blockIdx.x;
     const int l1 = a.l1[p], l2 = a.l2[p];
@@ -86,8 +93,19 @@ __global__ void __launch_bounds__(kThreejThreads) threej_rows_kernel(ThreejArgs 
     }
     const long long jmin = l1 > l2 ? l1 - l2 : l2 - l1;
     const long long n = (long long)l1 + l2 - jmin + 1;
-    for (long long i = threadIdx.x; i < a.stride; i += kThreejThreads)
-        row[i] = i < n ? symbol(a, l1, l2, jmin + i) : 0.0;
+    for (long long i0 = threadIdx.x; i0 < a.stride; i0 += (long long)kThreejThreads * kThreejBatch) {
+        double v[kThreejBatch];
+#pragma unroll
+        for (int q = 0; q < kThreejBatch; ++q) {
+            const long long i = i0 + (long long)q * kThreejThreads;
+            v[q] = i < n ? symbol(a, l1, l2, jmin + i) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kThreejBatch; ++q) {
+            const long long i = i0 + (long long)q * kThreejThreads;
+            if (i < a.stride) row[i] = v[q];
+        }
+    }
 }
 
 }  // namespace
