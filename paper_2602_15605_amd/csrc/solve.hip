@@ -63,25 +63,39 @@ struct SolveArgs {
     int n, m, n_rhs, pol;
 };
 
-// The value lane 0 holds, in every lane.
-__device__ inline double lane0_double(double v) {
+// One step of the arg-max: the pair of the lane that DPP control Ctrl names
+// (a row shift or a row broadcast; rows outside RowMask and lanes with no
+// source keep their own pair) replaces this lane's pair if it is larger.
+template <int Ctrl, int RowMask>
+__device__ inline void argmax_dpp_step(double& v, int& idx) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    const int lo = (int)(b & 0xffffffff), hi = (int)(b >> 32);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, Ctrl, RowMask, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, Ctrl, RowMask, 0xf, false);
+    const int oi = __builtin_amdgcn_update_dpp(idx, idx, Ctrl, RowMask, 0xf, false);
+    const double ov = __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
+    if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+    }
 }
 
-// Largest (|v|, first row on ties) of the candidates of one wave, in lane 0.
+// Largest (|v|, first row on ties) over the 64 lanes of a wave (all active),
+// returned in every lane.  Shifts by 1, 2, 4, 8 within each row of 16 lanes
+// leave each row's result in its lane 15; broadcasting lane 15 into the next
+// row and lane 31 into rows 2 and 3 leaves the wave's result in lane 63.
 __device__ inline void wave_argmax(double& v, int& idx) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double ov = __shfl_down(v, off, kWave);
-        const int oi = __shfl_down(idx, off, kWave);
-        if (ov > v || (ov == v && oi < idx)) {
-            v = ov;
-            idx = oi;
-        }
-    }
+    argmax_dpp_step<0x111, 0xf>(v, idx);    // row_shr:1
+    argmax_dpp_step<0x112, 0xf>(v, idx);    // row_shr:2
+    argmax_dpp_step<0x114, 0xf>(v, idx);    // row_shr:4
+    argmax_dpp_step<0x118, 0xf>(v, idx);    // row_shr:8
+    argmax_dpp_step<0x142, 0xa>(v, idx);    // row_bcast:15 into rows 1 and 3
+    argmax_dpp_step<0x143, 0xc>(v, idx);    // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), kWave - 1);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), kWave - 1);
+    v = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    idx = __builtin_amdgcn_readlane(idx, kWave - 1);
 }
 
 // Panel of NB columns in LDS: rows k0 .. m-1 (at most kPanelDoubles / NB).
@@ -148,12 +162,11 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
                         }
                     }
                     wave_argmax(best, bi);
-                    best = lane0_double(best);
-                    bi = __builtin_amdgcn_readfirstlane(bi);
                     if (!(best > 0.0)) {         // zero (or NaN) pivot column: the system is singular
                         sing = true;
                         break;
                     }
+                    bi = min(max(bi, j), mr - 1);    // a candidate row of this column
                     if (lane < NB && bi != j) {
                         const double x = s_panel[j * NB + lane];
                         s_panel[j * NB + lane] = s_panel[bi * NB + lane];
@@ -207,11 +220,11 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
                     }
                 }
                 __syncthreads();
-                const int p = s_pi;
                 if (!(s_pv > 0.0)) {             // zero (or NaN) pivot column: the system is singular
                     singular = true;
                     break;
                 }
+                const int p = min(max(s_pi, j), mr - 1);    // a candidate row of this column
                 if (t < NB && p != j) {
                     const double x = s_panel[j * NB + t];
                     s_panel[j * NB + t] = s_panel[p * NB + t];
