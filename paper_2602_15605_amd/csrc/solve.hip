@@ -80,6 +80,14 @@ __device__ inline void argmax_dpp_step(double& v, int& idx) {
     }
 }
 
+// The value of lane i (the same i in every lane) in every lane, from registers.
+__device__ inline double lane_value(double v, int i) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Largest (|v|, first row on ties) over the 64 lanes of a wave (all active),
 // returned in every lane.  Shifts by 1, 2, 4, 8 within each row of 16 lanes
 // leave each row's result in its lane 15; broadcasting lane 15 into the next
@@ -91,10 +99,7 @@ __device__ inline void wave_argmax(double& v, int& idx) {
     argmax_dpp_step<0x118, 0xf>(v, idx);    // row_shr:8
     argmax_dpp_step<0x142, 0xa>(v, idx);    // row_bcast:15 into rows 1 and 3
     argmax_dpp_step<0x143, 0xc>(v, idx);    // row_bcast:31 into rows 2 and 3
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), kWave - 1);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), kWave - 1);
-    v = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    v = lane_value(v, kWave - 1);
     idx = __builtin_amdgcn_readlane(idx, kWave - 1);
 }
 
@@ -332,7 +337,7 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
             for (int c = wave; c < rc; c += kSolveWaves) {
                 double xv = lane < bs ? Xs[(ib + lane) * rc + c] : 0.0;
                 for (int i = bs - 1; i >= 0; --i) {
-                    const double xi = __shfl(xv, i, kWave) / Ub[i * (kBackBlock + 1) + i];
+                    const double xi = lane_value(xv, i) / Ub[i * (kBackBlock + 1) + i];
                     if (lane == i) xv = xi;
                     else if (lane < i) xv = __builtin_fma(-Ub[lane * (kBackBlock + 1) + i], xi, xv);
                 }
