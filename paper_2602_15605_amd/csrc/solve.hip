@@ -13,7 +13,9 @@
 // block system for E/B) in the caller's workspace and runs a blocked LU with
 // partial pivoting (largest |pivot|, the first row on ties):
 //   * a panel of NB columns (8, or 4 when the rows would not fit) is
-//     factorised in LDS by one wave, with no work-group barrier per column;
+//     factorised in LDS: by one wave, with no work-group barrier per column,
+//     when it has at most kWavePanelRows rows, else by every wave; the
+//     pivot's arg-max over a wave runs on DPP lane moves;
 //   * right of the panel, each column applies the panel's row exchanges and
 //     the unit-lower forward substitution U12 = L11^-1 A12;
 //   * the trailing block gets A22 -= L21 U12: lanes over 64 consecutive
