@@ -5,7 +5,8 @@ against the oracle (oracle/master.py, numpy's LAPACK solve).
 * Random TT and E/B block systems, one and several right-hand sides, a system
   that needs row exchanges: agreement with numpy within a bound from the
   condition number.
-* A singular system gives NaN; argument errors are caught on the host.
+* A singular system gives NaN (small, and 700 unknowns through the tall
+  panels); argument errors are caught on the host.
 * End to end: windows -> binned K (couple_band) -> pseudo-spectra of a C_l
   that is constant inside each bin -> solve.  For such a C_l the binned
   relation of Sec. 2 eq. pseudo_cl is exact, so the solve must return the
@@ -139,6 +140,25 @@ def test_singular_system_gives_nan(torch_gpu, ctx):
     # a good system on the same context right after
     x = couple.couple_master_solve(ctx, _gpu(torch, 4.0 * np.eye(3)), _gpu(torch, np.ones(3))).cpu().numpy()
     assert np.array_equal(x, np.full(3, 0.25))
+
+
+def test_singular_tall_system_gives_nan(torch_gpu, ctx):
+    """Two equal rows in a 700-unknown system (panels taller than one wave
+    handles, then short ones): both rows get the same updates, so when one
+    becomes a pivot the other is reduced to exact zeros and a later pivot
+    column is zero."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    rng = np.random.default_rng(700)
+    A = _system(700, rng)
+    A[650] = A[10]
+    x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, rng.standard_normal((2, 700)))).cpu().numpy()
+    assert x.shape == (2, 700) and np.all(np.isnan(x))
+    # the same system with the row restored solves
+    A[650] = _system(700, np.random.default_rng(700))[650]
+    b = rng.standard_normal(700)
+    x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, b)).cpu().numpy()
+    _check_solution(x, A, b, "restored 700")
 
 
 def test_argument_errors(torch_gpu, ctx):
