@@ -142,7 +142,8 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
     if (even) {
         Timed t(ctx, s, 1);
-        e = couple::launch_strip(ctx, lmax, pol ? couple::kStripPol : couple::kStripTT, precision, l3_lo,
+        const int mode = !pol ? couple::kStripTT : (spectra & COUPLE_TE) ? couple::kStripPol : couple::kStripPolEE;
+        e = couple::launch_strip(ctx, lmax, mode, precision, l3_lo,
                                  std::min(l3_hi, 2 * lmax), s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "strip launch");

@@ -141,8 +141,9 @@ struct Win {
     __device__ static inline int phys(int slot) { return slot + slot / R; }
 };
 
-// Kernel modes: TT only; TT + TE + EE (even L); EB (odd L).
-enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2 };
+// Kernel modes: TT only; TT + TE + EE (even L); EB (odd L); TT + EE (even L,
+// no TE: the TE window is not staged and its sum is not formed).
+enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2, kModePolEE = 3 };
 
 // WIDE (lmax > kNarrowLmax): a(a-2) + b(b-2) exceeds 2^53 and N' cancels
 // against it when l1 << l2, so N' is taken as t^2 - (2ab + 1) with t exact and
@@ -152,7 +153,8 @@ constexpr int kNarrowLmax = 8000;
 template <int R, int MODE, bool WIDE>
 __global__ void __launch_bounds__(kWave)
 strip_fp64_kernel(StripArgs a) {
-    constexpr bool POL = MODE == kModePol;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE;
+    constexpr bool TE = MODE == kModePol;
     constexpr bool EB = MODE == kModeEB;
     constexpr int KC = kStripChunkF64;
     using W = Win<R, KC>;
@@ -238,7 +240,7 @@ strip_fp64_kernel(StripArgs a) {
                 gb[e] = a.g[de + k];
                 if (EB || POL) w2[e] = wpp[l3];
                 if (!EB) w0[e] = wtt[l3];
-                if (POL) w1[e] = wtp[l3];
+                if (TE) w1[e] = wtp[l3];
             }
         }
 #pragma unroll
@@ -256,7 +258,7 @@ strip_fp64_kernel(StripArgs a) {
                 } else {
                     u.x = w0[e] * gg;
                     if (POL) {
-                        u.y = w1[e] * gg;
+                        if (TE) u.y = w1[e] * gg;
                         u.z = w2[e] * gg;
                         u.w = (double)c;
                     }
@@ -314,7 +316,7 @@ strip_fp64_kernel(StripArgs a) {
                             N = __builtin_fma(uu.w, dc, kap[j]);
                         }
                         const double y = P * N;
-                        te[j] = __builtin_fma(uu.y, y, te[j]);
+                        if (TE) te[j] = __builtin_fma(uu.y, y, te[j]);
                         const double z = y * N;
                         ee[j] = __builtin_fma(uu.z, z, ee[j]);
                     }
@@ -337,7 +339,7 @@ strip_fp64_kernel(StripArgs a) {
             a.xi[off + l1] = tt[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
-                a.xi[a.xi_stride + off + l1] = s * te[j];
+                if (TE) a.xi[a.xi_stride + off + l1] = s * te[j];
                 a.xi[2 * a.xi_stride + off + l1] = (s * s) * ee[j];
             }
         }
@@ -378,7 +380,8 @@ constexpr int kCompPeriod = 64;
 template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
 strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
-    constexpr bool POL = MODE == kModePol;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE;
+    constexpr bool TE = MODE == kModePol;
     constexpr bool EB = MODE == kModeEB;
     constexpr int KC = kStripChunkF32;
     using W = Win<R, KC>;
@@ -463,7 +466,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                 } else {
                     u.x = (float)(wtt[l3] * gg);
                     if (POL) {
-                        u.y = (float)(wtp[l3] * gg);
+                        if (TE) u.y = (float)(wtp[l3] * gg);
                         u.z = (float)(wpp[l3] * gg);
                         u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
                     }
@@ -532,7 +535,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                             const float t = j == 0 ? t0 : t0 - dg[j];
                             const float N = __builtin_fmaf(t, t, -beta[j]);
                             const float y = P * N;
-                            bte[j] = __builtin_fmaf(uu.y, y, bte[j]);
+                            if (TE) bte[j] = __builtin_fmaf(uu.y, y, bte[j]);
                             const float z = y * N;
                             bee[j] = __builtin_fmaf(uu.z, z, bee[j]);
                         }
@@ -543,10 +546,8 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 mt[j] += bt[j];
-                if (POL) {
-                    mte[j] += bte[j];
-                    mee[j] += bee[j];
-                }
+                if (TE) mte[j] += bte[j];
+                if (POL) mee[j] += bee[j];
             }
             if ((sb + G) % CP != 0 && sb + G < kc_r) continue;
             // Kahan step: mid sums into the pairs
@@ -559,16 +560,19 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     kt[j] = tv;
                     mt[j] = 0.0f;
                 }
-                if (POL) {
+                if (TE) {
                     const float yv = mte[j] - cte[j];
                     const float tv = kte[j] + yv;
                     cte[j] = (tv - kte[j]) - yv;
                     kte[j] = tv;
+                    mte[j] = 0.0f;
+                }
+                if (POL) {
                     const float yw = mee[j] - cee[j];
                     const float tw = kee[j] + yw;
                     cee[j] = (tw - kee[j]) - yw;
                     kee[j] = tw;
-                    mte[j] = mee[j] = 0.0f;
+                    mee[j] = 0.0f;
                 }
             }
         }
@@ -587,7 +591,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             a.xi[off + l1] = (double)kt[j] - (double)ct[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
-                a.xi[a.xi_stride + off + l1] = s * ((double)kte[j] - (double)cte[j]);
+                if (TE) a.xi[a.xi_stride + off + l1] = s * ((double)kte[j] - (double)cte[j]);
                 a.xi[2 * a.xi_stride + off + l1] = (s * s) * ((double)kee[j] - (double)cee[j]);
             }
         }
@@ -643,6 +647,8 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeEB>), grid, block, 0, s, a, gf, hf);
         else if (mode == kStripPol)
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModePol>), grid, block, 0, s, a, gf, hf);
+        else if (mode == kStripPolEE)
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModePolEE>), grid, block, 0, s, a, gf, hf);
         else
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeTT>), grid, block, 0, s, a, gf, hf);
     } else {
@@ -652,6 +658,10 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol, true>), grid, block, 0, s, a);
         else if (mode == kStripPol)
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModePol, false>), grid, block, 0, s, a);
+        else if (mode == kStripPolEE && lmax > kNarrowLmax)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePolEE, true>), grid, block, 0, s, a);
+        else if (mode == kStripPolEE)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModePolEE, false>), grid, block, 0, s, a);
         else
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT, false>), grid, block, 0, s, a);
     }
