@@ -76,18 +76,21 @@ def test_workload4_band_binned_8_masks(torch_gpu, ctx, oracle_bulk):
     assert np.array_equal(Kb[:, 1], Kb[:, 2])
 
 
-def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk):
+@pytest.mark.parametrize("spectra", [("TT", "TE", "EE"), ("EE", "BB")])
+def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk, spectra):
+    """Sampled rows of the unbinned band at lmax = 10000 in FP64 (the wide
+    N' form), with TE and without it (the TT + EE kernel mode)."""
     from paper_2602_15605_amd import couple, synth
     torch = torch_gpu
     W = synth.workload_windows(4, mask=0)
     dW = [torch.as_tensor(w).cuda() for w in W]
-    K = couple.couple_band(ctx, 0, LCUT, dW[0], dW[1], dW[2], LMAX, spectra=("TT", "TE", "EE"), precision="fp64")
+    K = couple.couple_band(ctx, 0, LCUT, dW[0], dW[1], dW[2], LMAX, spectra=spectra, precision="fp64")
     rows = np.array([0, 1, 2, 3, 999, 1000, 1001, 4321, 9000, 9999, 10000])
     got = K[:, torch.as_tensor(rows).cuda(), :].cpu().numpy()
     del K
-    Kr, Ar = oracle_bulk.coupling_rows(LMAX, *W, rows=rows, spectra=("TT", "TE", "EE"), l3_range=(0, LCUT),
+    Kr, Ar = oracle_bulk.coupling_rows(LMAX, *W, rows=rows, spectra=spectra, l3_range=(0, LCUT),
                                        band_forward=True)
-    for i, s in enumerate(("TT", "TE", "EE")):
+    for i, s in enumerate(spectra):
         err = assert_parity(got[i], Kr[i], Ar[i], TOL_FP64, "band unbinned %s" % s)
         _say("band unbinned fp64 %s max rel err %.3e" % (s, err))
 
