@@ -54,14 +54,14 @@ __device__ inline double x000(const ThreejArgs& a, long long j1, long long j2, l
     return (P & 1) ? -v : v;
 }
 
-// Both parities share one (0 0 0) evaluation: (l1 l2 l3) for even L and
-// (l1, l2+1, l3) for odd L, whose total is then even.  Neighbouring l3
-// alternate in parity, so the two factors are both formed and one is selected
-// per lane, which keeps the wave on a single path.  For m = 1, 2 the factor of
-// the parity not taken can be the root of a negative number; it is discarded.
-__device__ inline double symbol(const ThreejArgs& a, long long l1, long long l2, long long l3) {
+// m = 1, 2, with rowf from row_factor.  Both parities share one (0 0 0)
+// evaluation: (l1 l2 l3) for even L and (l1, l2+1, l3) for odd L, whose total
+// is then even.  Neighbouring l3 alternate in parity, so the two factors are
+// both formed and one is selected per lane, which keeps the wave on a single
+// path.  The factor of the parity not taken can be the root of a negative
+// number; it is discarded.
+__device__ inline double symbol(const ThreejArgs& a, long long l1, long long l2, long long l3, double rowf) {
     const long long L = l1 + l2 + l3;
-    if (a.m == 0) return x000(a, l1, l2, l3);
     const long long odd = L & 1;
     const double x = x000(a, l1, l2 + odd, l3);
     const long long A = l1 * (l1 + 1), B = l2 * (l2 + 1), C = l3 * (l3 + 1);
@@ -69,20 +69,29 @@ __device__ inline double symbol(const ThreejArgs& a, long long l1, long long l2,
         if (l1 < 1 || l2 < 1) return 0.0;
         const double num = (double)((L + 2) * (L - 2 * l3 + 1)) * (double)((L - 2 * l1 + 1) * (L - 2 * l2));
         const double f = odd ? sqrt(num) : (double)(A + B - C);
-        return -0.5 * f / sqrt((double)A * (double)B) * x;
+        return f * rowf * x;
     }
     if (l1 < 2 || l2 < 2) return 0.0;
-    const double s = 0.5 * a.cl[l1] * a.cl[l2];
     const long long np = C * (C - 2 * (A + B - 1)) + A * (A - 2) + B * (B - 2);
     const long long sg = l1 + l2 + 1, tau = sg + 1, d = l2 - l1;
     const long long mu = 2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1);
     const long long f1 = sg * (sg + 1) - C, f2 = C - d * (d + 1);
     const double f = odd ? -(double)(C + mu) * sqrt((double)f1 * (double)f2) : (double)np;
-    return x * f * s;
+    return x * f * rowf;
+}
+
+// The factor shared by a whole row: m = 1: -1 / (2 sqrt(a b)); m = 2: c_l1 c_l2 / 2.
+__device__ inline double row_factor(const ThreejArgs& a, long long l1, long long l2) {
+    if (a.m == 1) return (l1 < 1 || l2 < 1) ? 0.0 : -0.5 / sqrt((double)(l1 * (l1 + 1)) * (double)(l2 * (l2 + 1)));
+    if (a.m == 2) return (l1 < 2 || l2 < 2) ? 0.0 : 0.5 * a.cl[l1] * a.cl[l2];
+    return 1.0;
 }
 
 // Each thread computes kThreejBatch symbols of its row before it stores any,
-// so their table reads are in flight together.
+// so their table reads are in flight together.  For m = 0 the symbols of odd
+// L vanish; a row starts at L = 2 max(l1, l2), so its even entries are the
+// even-L ones, and each thread takes a pair of entries: it evaluates the even
+// one and writes a zero beside it.
 __global__ void __launch_bounds__(kThreejThreads) threej_rows_kernel(ThreejArgs a) {
     const long long p = blockIdx.x;
     const int l1 = a.l1[p], l2 = a.l2[p];
@@ -93,12 +102,30 @@ __global__ void __launch_bounds__(kThreejThreads) threej_rows_kernel(ThreejArgs 
     }
     const long long jmin = l1 > l2 ? l1 - l2 : l2 - l1;
     const long long n = (long long)l1 + l2 - jmin + 1;
+    if (a.m == 0) {
+        for (long long q0 = threadIdx.x; 2 * q0 < a.stride; q0 += (long long)kThreejThreads * kThreejBatch) {
+            double v[kThreejBatch];
+#pragma unroll
+            for (int q = 0; q < kThreejBatch; ++q) {
+                const long long i = 2 * (q0 + (long long)q * kThreejThreads);
+                v[q] = i < n ? x000(a, l1, l2, jmin + i) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kThreejBatch; ++q) {
+                const long long i = 2 * (q0 + (long long)q * kThreejThreads);
+                if (i < a.stride) row[i] = v[q];
+                if (i + 1 < a.stride) row[i + 1] = 0.0;
+            }
+        }
+        return;
+    }
+    const double rowf = row_factor(a, l1, l2);
     for (long long i0 = threadIdx.x; i0 < a.stride; i0 += (long long)kThreejThreads * kThreejBatch) {
         double v[kThreejBatch];
 #pragma unroll
         for (int q = 0; q < kThreejBatch; ++q) {
             const long long i = i0 + (long long)q * kThreejThreads;
-            v[q] = i < n ? symbol(a, l1, l2, jmin + i) : 0.0;
+            v[q] = i < n ? symbol(a, l1, l2, jmin + i, rowf) : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < kThreejBatch; ++q) {

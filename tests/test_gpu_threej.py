@@ -111,8 +111,10 @@ def test_invalid_pairs_and_short_stride(torch_gpu, ctx, oracle_bulk):
     assert np.all(np.isnan(got[1])) and np.all(np.isnan(got[2])) and np.all(np.isnan(got[3]))
     ref = oracle_bulk.threej_row(10, 12, -2)
     assert np.allclose(got[0, :len(ref)], ref, rtol=0, atol=1e-15)
-    short = couple.couple_threej_rows(ctx, [300], [400], 1, stride=50).cpu().numpy()
-    full = couple.couple_threej_rows(ctx, [300], [400], 1).cpu().numpy()
-    assert short.shape == (1, 50) and np.array_equal(short[0], full[0, :50])
+    for m in (0, 1, 2):
+        full = couple.couple_threej_rows(ctx, [300], [400], m).cpu().numpy()
+        for stride in (50, 51):                  # even and odd row lengths
+            short = couple.couple_threej_rows(ctx, [300], [400], m, stride=stride).cpu().numpy()
+            assert short.shape == (1, stride) and np.array_equal(short[0], full[0, :stride]), (m, stride)
     with pytest.raises(couple.CoupleError):
         couple.couple_threej_rows(ctx, [1], [1], 3)
