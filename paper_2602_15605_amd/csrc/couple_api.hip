@@ -142,7 +142,10 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
     if (even) {
         Timed t(ctx, s, 1);
-        const int mode = !pol ? couple::kStripTT : (spectra & COUPLE_TE) ? couple::kStripPol : couple::kStripPolEE;
+        const int mode = !pol                    ? couple::kStripTT
+                         : (spectra & COUPLE_TE) ? couple::kStripPol
+                         : (spectra & COUPLE_TT) ? couple::kStripPolEE
+                                                 : couple::kStripEE;
         e = couple::launch_strip(ctx, lmax, mode, precision, l3_lo,
                                  std::min(l3_hi, 2 * lmax), s);
     }

@@ -69,7 +69,7 @@ hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
 
 // strip kernels (strip.hip): Xi on the packed upper triangle.
 //   mode kStripTT: Xi_TT; kStripPol: Xi_TT, Xi_TE, Xi_EE (even L); kStripPolEE:
-//   Xi_TT, Xi_EE (even L, for calls that ask for no TE);
+//   Xi_TT, Xi_EE (even L, for calls that ask for no TE); kStripEE: Xi_EE alone;
 //   kStripEB: Xi_EB (odd L, fourth triangle).  l3 restricted to [l3_lo, l3_hi].
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
                                 const double* wpp, int n, hipStream_t s);

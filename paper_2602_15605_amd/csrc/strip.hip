@@ -142,8 +142,9 @@ struct Win {
 };
 
 // Kernel modes: TT only; TT + TE + EE (even L); EB (odd L); TT + EE (even L,
-// no TE: the TE window is not staged and its sum is not formed).
-enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2, kModePolEE = 3 };
+// no TE: the TE window is not staged and its sum is not formed); EE only
+// (even L, neither TT nor TE).
+enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2, kModePolEE = 3, kModeEE = 4 };
 
 // WIDE (lmax > kNarrowLmax): a(a-2) + b(b-2) exceeds 2^53 and N' cancels
 // against it when l1 << l2, so N' is taken as t^2 - (2ab + 1) with t exact and
@@ -153,8 +154,9 @@ constexpr int kNarrowLmax = 8000;
 template <int R, int MODE, bool WIDE>
 __global__ void __launch_bounds__(kWave)
 strip_fp64_kernel(StripArgs a) {
-    constexpr bool POL = MODE == kModePol || MODE == kModePolEE;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
     constexpr bool TE = MODE == kModePol;
+    constexpr bool TTS = MODE != kModeEE;               // the first sum (TT, or EB's)
     constexpr bool EB = MODE == kModeEB;
     constexpr int KC = kStripChunkF64;
     using W = Win<R, KC>;
@@ -239,7 +241,7 @@ strip_fp64_kernel(StripArgs a) {
                 ga[e] = a.g[k];
                 gb[e] = a.g[de + k];
                 if (EB || POL) w2[e] = wpp[l3];
-                if (!EB) w0[e] = wtt[l3];
+                if (!EB && TTS) w0[e] = wtt[l3];
                 if (TE) w1[e] = wtp[l3];
             }
         }
@@ -256,7 +258,7 @@ strip_fp64_kernel(StripArgs a) {
                     u.x = w2[e] * gg * (double)(c - (long long)d * (d + 1));
                     u.w = (double)c;
                 } else {
-                    u.x = w0[e] * gg;
+                    if (TTS) u.x = w0[e] * gg;
                     if (POL) {
                         if (TE) u.y = w1[e] * gg;
                         u.z = w2[e] * gg;
@@ -305,7 +307,7 @@ strip_fp64_kernel(StripArgs a) {
                         tt[j] = __builtin_fma(uu.x, P * ((f1 * f3) * f3), tt[j]);
                         continue;
                     }
-                    tt[j] = __builtin_fma(uu.x, P, tt[j]);
+                    if (TTS) tt[j] = __builtin_fma(uu.x, P, tt[j]);
                     if (POL) {
                         double N;
                         if (WIDE) {
@@ -336,7 +338,7 @@ strip_fp64_kernel(StripArgs a) {
                 a.xi[3 * a.xi_stride + off + l1] = (s * s) * tt[j];
                 continue;
             }
-            a.xi[off + l1] = tt[j];
+            if (TTS) a.xi[off + l1] = tt[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
                 if (TE) a.xi[a.xi_stride + off + l1] = s * te[j];
@@ -380,8 +382,9 @@ constexpr int kCompPeriod = 64;
 template <int R, int MODE>
 __global__ void __launch_bounds__(kWave)
 strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
-    constexpr bool POL = MODE == kModePol || MODE == kModePolEE;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
     constexpr bool TE = MODE == kModePol;
+    constexpr bool TTS = MODE != kModeEE;               // the first sum (TT, or EB's)
     constexpr bool EB = MODE == kModeEB;
     constexpr int KC = kStripChunkF32;
     using W = Win<R, KC>;
@@ -464,7 +467,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     u.x = (float)(wpp[l3] * gg * (double)(c - (long long)d * (d + 1)));
                     u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
                 } else {
-                    u.x = (float)(wtt[l3] * gg);
+                    if (TTS) u.x = (float)(wtt[l3] * gg);
                     if (POL) {
                         if (TE) u.y = (float)(wtp[l3] * gg);
                         u.z = (float)(wpp[l3] * gg);
@@ -530,7 +533,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                             bt[j] = __builtin_fmaf(uu.x, P * ((f1 * f3) * f3), bt[j]);
                             continue;
                         }
-                        bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
+                        if (TTS) bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
                         if (POL) {
                             const float t = j == 0 ? t0 : t0 - dg[j];
                             const float N = __builtin_fmaf(t, t, -beta[j]);
@@ -545,7 +548,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             // block sums into the mid sums
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                mt[j] += bt[j];
+                if (TTS) mt[j] += bt[j];
                 if (TE) mte[j] += bte[j];
                 if (POL) mee[j] += bee[j];
             }
@@ -553,7 +556,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             // Kahan step: mid sums into the pairs
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                {
+                if (TTS) {
                     const float yv = mt[j] - ct[j];
                     const float tv = kt[j] + yv;
                     ct[j] = (tv - kt[j]) - yv;
@@ -588,7 +591,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                 a.xi[3 * a.xi_stride + off + l1] = (s * s) * ((double)kt[j] - (double)ct[j]);
                 continue;
             }
-            a.xi[off + l1] = (double)kt[j] - (double)ct[j];
+            if (TTS) a.xi[off + l1] = (double)kt[j] - (double)ct[j];
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
                 if (TE) a.xi[a.xi_stride + off + l1] = s * ((double)kte[j] - (double)cte[j]);
@@ -649,6 +652,8 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModePol>), grid, block, 0, s, a, gf, hf);
         else if (mode == kStripPolEE)
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModePolEE>), grid, block, 0, s, a, gf, hf);
+        else if (mode == kStripEE)
+            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeEE>), grid, block, 0, s, a, gf, hf);
         else
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeTT>), grid, block, 0, s, a, gf, hf);
     } else {
@@ -662,6 +667,10 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModePolEE, true>), grid, block, 0, s, a);
         else if (mode == kStripPolEE)
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModePolEE, false>), grid, block, 0, s, a);
+        else if (mode == kStripEE && lmax > kNarrowLmax)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEE, true>), grid, block, 0, s, a);
+        else if (mode == kStripEE)
+            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEE, false>), grid, block, 0, s, a);
         else
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT, false>), grid, block, 0, s, a);
     }

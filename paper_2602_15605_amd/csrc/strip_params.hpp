@@ -36,6 +36,6 @@ __host__ __device__ inline long long tri_size(int lmax) {
 }
 
 // Strip kernel modes: Xi_TT; Xi_TT, Xi_TE, Xi_EE (even L); Xi_EB (odd L).
-enum { kStripTT = 0, kStripPol = 1, kStripEB = 2, kStripPolEE = 3 };
+enum { kStripTT = 0, kStripPol = 1, kStripEB = 2, kStripPolEE = 3, kStripEE = 4 };
 
 }  // namespace couple

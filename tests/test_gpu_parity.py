@@ -103,19 +103,22 @@ def test_full_matrix_parity_small(torch_gpu, ctx, oracle_bulk, lmax, kind):
     assert np.array_equal(K[2], K[3])
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32c", TOL_FP32C)])
 @pytest.mark.parametrize("spectra", [("TT",), ("TE",), ("EE", "BB"), ("TT", "EE"), ("BB",)])
-def test_spectra_subsets(torch_gpu, ctx, oracle_bulk, spectra):
+def test_spectra_subsets(torch_gpu, ctx, oracle_bulk, spectra, precision, tol):
+    """Each subset runs the kernel mode it selects (TT only; all three even-L
+    sums when TE is asked for; TT + EE; EE alone)."""
     lmax = 130
     Ws = _windows(lmax, 7)
     Wuse = [Ws[0] if "TT" in spectra else None, Ws[1] if "TE" in spectra else None,
             Ws[2] if ("EE" in spectra or "BB" in spectra) else None]
     from paper_2602_15605_amd import couple
     dW = [_gpu(torch_gpu, w) if w is not None else None for w in Wuse]
-    K = couple.couple_matrix(ctx, dW[0], dW[1], dW[2], lmax, spectra=spectra).cpu().numpy()
+    K = couple.couple_matrix(ctx, dW[0], dW[1], dW[2], lmax, spectra=spectra, precision=precision).cpu().numpy()
     Kr, Ar = _oracle(oracle_bulk, Ws, lmax, spectra=spectra)
     assert K.shape[0] == len(spectra)
     for i, s in enumerate(spectra):
-        assert_parity(K[i], Kr[i], Ar[i], TOL_FP64, s)
+        assert_parity(K[i], Kr[i], Ar[i], tol, s)
 
 
 def test_workload0_tt_lmax256(torch_gpu, ctx, oracle_bulk):
