@@ -639,6 +639,19 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     a.l3_lo = l3_lo;
     a.l3_hi = l3_hi;
     a.band = a.dmax < lmax ? 1 : 0;
+    if (mode == kStripTT) {
+        constexpr int RT = kStripRTT;
+        const long long n_tt = count_items(lmax, a.dmax, kWave * RT, a.band != 0);
+        if (n_tt <= 0) return hipSuccess;
+        if (n_tt > 0x7fffffffLL) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)n_tt), block(kWave);
+        if (precision == COUPLE_FP32C)
+            hipLaunchKernelGGL((strip_fp32c_kernel<RT, kModeTT>), grid, block, 0, s, a, ctx->gf_pad + kTablePad,
+                               ctx->hf_pad + kTablePad);
+        else
+            hipLaunchKernelGGL((strip_fp64_kernel<RT, kModeTT, false>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
     const long long n_items = count_items(lmax, a.dmax, kWave * R, a.band != 0);
     if (n_items <= 0) return hipSuccess;
     if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -655,7 +668,7 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
         else if (mode == kStripEE)
             hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeEE>), grid, block, 0, s, a, gf, hf);
         else
-            hipLaunchKernelGGL((strip_fp32c_kernel<R, kModeTT>), grid, block, 0, s, a, gf, hf);
+            return hipErrorInvalidValue;
     } else {
         if (mode == kStripEB)
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEB, false>), grid, block, 0, s, a);
@@ -672,7 +685,7 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
         else if (mode == kStripEE)
             hipLaunchKernelGGL((strip_fp64_kernel<R, kModeEE, false>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((strip_fp64_kernel<R, kModeTT, false>), grid, block, 0, s, a);
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

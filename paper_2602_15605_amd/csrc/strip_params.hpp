@@ -13,6 +13,9 @@ constexpr int kWave = 64;
 // G/H windows slide by one per l3 step, so each step loads one new G and
 // one new H value per lane for R terms.
 constexpr int kStripR = 4;
+// The TT-only sum costs two operations per term, so there the two window
+// reads per step dominate; eight rows per lane halve them per term.
+constexpr int kStripRTT = 8;
 
 // l3 steps staged in LDS per chunk by the float64 and float32 strip kernels.
 constexpr int kStripChunkF64 = 256;
