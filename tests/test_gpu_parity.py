@@ -468,3 +468,17 @@ def test_ragged_bins_all_spectra(torch_gpu, ctx, precision):
                     assert np.all(Kb[:, b, c] == 0.0)
         assert np.array_equal(Kb[2], Kb[3])          # K^BB shares K^EE's sums
         _say("ragged bins %s l3 in [%d, %d]: ok" % (precision, lo, hi))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32c", TOL_FP32C)])
+def test_band_tt_only(torch_gpu, ctx, oracle_bulk, precision, tol):
+    """K^TT alone, band-limited below lmax (the band grid of the TT-only mode,
+    eight rows per lane), against the oracle's band tier."""
+    from paper_2602_15605_amd import couple
+    lmax, lo, hi = 600, 5, 300
+    Ws = _windows(lmax, 61)
+    K = couple.couple_band(ctx, lo, hi, _gpu(torch_gpu, Ws[0]), None, None, lmax, spectra=("TT",),
+                           precision=precision).cpu().numpy()
+    Kr, Ar = _oracle(oracle_bulk, Ws, lmax, spectra=("TT",), l3_range=(lo, hi))
+    err = assert_parity(K[0], Kr[0], Ar[0], tol, "band TT %s" % precision)
+    _say("band TT only %s max rel err %.3e" % (precision, err))
