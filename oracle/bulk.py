@@ -45,6 +45,8 @@ def _load():
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.oracle_coupling_rows.restype = ctypes.c_int
+        lib.oracle_coupling_rows_upper.argtypes = lib.oracle_coupling_rows.argtypes + [ctypes.c_int]
+        lib.oracle_coupling_rows_upper.restype = ctypes.c_int
         lib.oracle_band_rows.argtypes = lib.oracle_coupling_rows.argtypes
         lib.oracle_band_rows.restype = ctypes.c_int
         lib.oracle_threej_row_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -85,14 +87,16 @@ def _as_f64(w):
 
 
 def coupling_rows(lmax, W_TT=None, W_TP=None, W_PP=None, rows=None, spectra=("TT",),
-                  l3_range=None, n_threads=0, with_abs=True, band_forward=False):
+                  l3_range=None, n_threads=0, with_abs=True, band_forward=False, upper=False):
     """K rows (and the |term| sums) for the requested l1 rows and spectra.
 
     Returns ``(K, A)`` with shapes [len(spectra), len(rows), lmax+1]; spectra
     are returned in the order given.  ``l3_range=(lo, hi)`` restricts the l3
     sum (band-limited kernels).  ``band_forward`` builds each row only up to
     l3 = hi by the forward recursion from its exact lower end (cost O(hi) per
-    element instead of O(l1 + l2)); it requires ``l3_range``.
+    element instead of O(l1 + l2)); it requires ``l3_range``.  ``upper``
+    evaluates only the entries l2 >= l1 of each row and leaves the others 0
+    (full-recursion rows only).
     """
     spectra = tuple(spectra)
     bits = 0
@@ -106,12 +110,18 @@ def coupling_rows(lmax, W_TT=None, W_TP=None, W_PP=None, rows=None, spectra=("TT
     K = np.zeros((len(order), len(rows), lmax + 1), dtype=np.float64)
     A = np.zeros_like(K) if with_abs else None
     ptr = [w.ctypes.data if w is not None else None for w in ws]
-    fn = _load().oracle_band_rows if band_forward else _load().oracle_coupling_rows
     if band_forward and l3_range is None:
         raise ValueError("band_forward needs l3_range")
-    rc = fn(int(lmax), ptr[0], ptr[1], ptr[2], int(w_len), lo, hi,
-                                      rows.ctypes.data, len(rows), bits, K.ctypes.data,
-                                      A.ctypes.data if A is not None else None, int(n_threads))
+    if band_forward and upper:
+        raise ValueError("upper applies to full-recursion rows only")
+    args = [int(lmax), ptr[0], ptr[1], ptr[2], int(w_len), lo, hi, rows.ctypes.data, len(rows), bits,
+            K.ctypes.data, A.ctypes.data if A is not None else None, int(n_threads)]
+    if band_forward:
+        rc = _load().oracle_band_rows(*args)
+    elif upper:
+        rc = _load().oracle_coupling_rows_upper(*args, 1)
+    else:
+        rc = _load().oracle_coupling_rows(*args)
     if rc != 0:
         raise RuntimeError("oracle_coupling_rows failed (%d)" % rc)
     idx = [order.index(s) for s in spectra]

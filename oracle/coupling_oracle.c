@@ -180,19 +180,65 @@ static int popcount5(unsigned x)
 }
 
 /*
+ * One K element for every selected spectrum: acc[k] and aab[k] (k in the
+ * order TT, TE, EE, BB, EB) receive sum_l3 (2 l3 + 1) W S and the sum of the
+ * absolute values of those terms, over l3 in [l3_lo, l3_hi].  x, z: rows of
+ * length 2 lmax + 2; fw, bw: scratch of the same length.
+ */
+static void coupling_element(int l1, int l2, const double *W_TT, const double *W_TP, const double *W_PP,
+                             int l3_lo, int l3_hi, unsigned spectra, ld *x, ld *z, ld *fw, ld *bw,
+                             ld *acc, ld *aab)
+{
+    const int need_pol = (spectra & (ORACLE_TE | ORACLE_EE | ORACLE_BB | ORACLE_EB)) != 0;
+    const long jmin = labs((long)l1 - l2);
+    long n, i;
+    int k;
+    for (k = 0; k < 5; ++k) acc[k] = aab[k] = 0.0L;
+    n = sg_row(l1, l2, 0, x, fw, bw);
+    if (need_pol) sg_row(l1, l2, -2, z, fw, bw);
+    for (i = 0; i < n; ++i) {
+        const long l3 = jmin + i;
+        const ld w3 = (ld)(2 * l3 + 1);
+        const int even = ((l1 + l2 + l3) & 1L) == 0;
+        ld t;
+        if (l3 < l3_lo || l3 > l3_hi) continue;
+        if (spectra & ORACLE_TT) {
+            t = w3 * (ld)W_TT[l3] * x[i] * x[i];
+            acc[0] += t; aab[0] += fabsl(t);
+        }
+        if ((spectra & ORACLE_TE) && even) {
+            t = w3 * (ld)W_TP[l3] * x[i] * z[i];
+            acc[1] += t; aab[1] += fabsl(t);
+        }
+        if ((spectra & ORACLE_EE) && even) {
+            t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+            acc[2] += t; aab[2] += fabsl(t);
+        }
+        if ((spectra & ORACLE_BB) && even) {
+            t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+            acc[3] += t; aab[3] += fabsl(t);
+        }
+        if ((spectra & ORACLE_EB) && !even) {
+            t = w3 * (ld)W_PP[l3] * z[i] * z[i];
+            acc[4] += t; aab[4] += fabsl(t);
+        }
+    }
+}
+
+/*
  * K rows.  rows[0..n_rows-1] are the l1 values; every l2 in 0..lmax is
- * evaluated.  Only l3 in [l3_lo, l3_hi] enter the sum (pass 0 and a large
- * value for the full sum).  Output K_out and A_out (may be NULL) are
+ * evaluated, or with `upper` set only l2 >= l1 (the other entries are left
+ * 0).  Only l3 in [l3_lo, l3_hi] enter the sum (pass 0 and a large value for
+ * the full sum).  Output K_out and A_out (may be NULL) are
  * [n_sel][n_rows][lmax+1] float64, n_sel = popcount(spectra), in the order
  * TT, TE, EE, BB, EB.  Returns 0, or a negative value on bad arguments.
  */
-int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const double *W_PP,
-                         int w_len, int l3_lo, int l3_hi, const int *rows, int n_rows,
-                         unsigned spectra, double *K_out, double *A_out, int n_threads)
+int oracle_coupling_rows_upper(int lmax, const double *W_TT, const double *W_TP, const double *W_PP,
+                               int w_len, int l3_lo, int l3_hi, const int *rows, int n_rows,
+                               unsigned spectra, double *K_out, double *A_out, int n_threads, int upper)
 {
     const int n_sel = popcount5(spectra & 31u);
     const long ncol = (long)lmax + 1;
-    const int need_pol = (spectra & (ORACLE_TE | ORACLE_EE | ORACLE_BB | ORACLE_EB)) != 0;
     int r, err = 0;
     if (lmax < 0 || n_rows < 0 || !rows || !K_out || n_sel == 0) return -1;
     if (w_len < 2 * lmax + 1) return -1;
@@ -202,6 +248,10 @@ int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const
     for (r = 0; r < n_rows; ++r)
         if (rows[r] < 0 || rows[r] > lmax) return -1;
     if (n_threads > 0) omp_set_num_threads(n_threads);
+    if (upper) {
+        memset(K_out, 0, sizeof(double) * (size_t)n_sel * n_rows * ncol);
+        if (A_out) memset(A_out, 0, sizeof(double) * (size_t)n_sel * n_rows * ncol);
+    }
 
 #pragma omp parallel reduction(| : err)
     {
@@ -215,41 +265,12 @@ int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const
             const int l1 = rows[task / ncol];
             const int l2 = (int)(task % ncol);
             const long ri = task / ncol;
-            const long jmin = labs((long)l1 - l2);
-            long n, i;
-            ld acc[5] = {0, 0, 0, 0, 0}, aab[5] = {0, 0, 0, 0, 0};
+            ld acc[5], aab[5];
             ld pref;
             int k, o;
-            if (err) continue;
-            n = sg_row(l1, l2, 0, x, x + len, x + 2 * len);
-            if (need_pol) sg_row(l1, l2, -2, z, x + len, x + 2 * len);
-            for (i = 0; i < n; ++i) {
-                const long l3 = jmin + i;
-                const ld w3 = (ld)(2 * l3 + 1);
-                const int even = ((l1 + l2 + l3) & 1L) == 0;
-                ld t;
-                if (l3 < l3_lo || l3 > l3_hi) continue;
-                if (spectra & ORACLE_TT) {
-                    t = w3 * (ld)W_TT[l3] * x[i] * x[i];
-                    acc[0] += t; aab[0] += fabsl(t);
-                }
-                if ((spectra & ORACLE_TE) && even) {
-                    t = w3 * (ld)W_TP[l3] * x[i] * z[i];
-                    acc[1] += t; aab[1] += fabsl(t);
-                }
-                if ((spectra & ORACLE_EE) && even) {
-                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
-                    acc[2] += t; aab[2] += fabsl(t);
-                }
-                if ((spectra & ORACLE_BB) && even) {
-                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
-                    acc[3] += t; aab[3] += fabsl(t);
-                }
-                if ((spectra & ORACLE_EB) && !even) {
-                    t = w3 * (ld)W_PP[l3] * z[i] * z[i];
-                    acc[4] += t; aab[4] += fabsl(t);
-                }
-            }
+            if (err || (upper && l2 < l1)) continue;
+            coupling_element(l1, l2, W_TT, W_TP, W_PP, l3_lo, l3_hi, spectra, x, z, x + len, x + 2 * len,
+                             acc, aab);
             pref = (ld)(2 * l2 + 1) / (4.0L * PI_L);
             for (k = 0, o = 0; k < 5; ++k) {
                 if (!(spectra & (1u << k))) continue;
@@ -262,6 +283,14 @@ int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const
         free(z);
     }
     return err ? -2 : 0;
+}
+
+int oracle_coupling_rows(int lmax, const double *W_TT, const double *W_TP, const double *W_PP,
+                         int w_len, int l3_lo, int l3_hi, const int *rows, int n_rows,
+                         unsigned spectra, double *K_out, double *A_out, int n_threads)
+{
+    return oracle_coupling_rows_upper(lmax, W_TT, W_TP, W_PP, w_len, l3_lo, l3_hi, rows, n_rows, spectra,
+                                      K_out, A_out, n_threads, 0);
 }
 
 /* ------------------------------------------------------------------------

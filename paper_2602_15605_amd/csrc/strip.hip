@@ -355,19 +355,24 @@ strip_fp64_kernel(StripArgs a) {
 //       double-double build),
 //   U_X(k) formed in float64 from the float64 tables and windows and rounded
 //       once to float32,
-//   N' = t^2 - (2ab + 1) with t = c - (a + b - 1).  The subtraction cancels
-//       (t is small when l1 << l2), so t is formed from exact pieces: per lane
-//       and split the integer T = c(split start) - (a + b - 1) is split into
-//       float32 T_hi + T_lo exactly, the staged per-step value is the integer
-//       D(k) = c(k) - c(split start) (|D| < 2^24, exact in float32; the split
-//       is rebased every kStripRebase steps), and
-//       t = T_hi + (D + T_lo) is rounded once -- two float32 adds instead of an
-//       integer subtraction and a half-rate int-to-float conversion.  Then
-//       one fused multiply-add gives N'.  Only a lane's first row takes the
-//       split; row j uses t_j = t_0 - (gam_j - gam_0), gam = a + b - 1, whose
-//       integer offset (below 2^19) is exact in float32: the subtraction is
-//       exact while |t_0| < 2^24 and otherwise adds one rounding of a value
-//       within 3 % of |t_0|, so t_j stays within 2^-23 relative.
+//   N' = t^2 - (2ab + 1) with t = c - (a + b - 1) is an integer polynomial in
+//       c, and both t^2 and 2ab + 1 exceed 2^24 for l >~ 2900 while N' may be
+//       much smaller, so it is expanded about the start of each split of
+//       kStripRebase steps: with the exact integers T = c_s - (a + b - 1) and
+//       Q = T^2 - (2ab + 1) = N'(c_s) at the split's c_s, and the staged
+//       per-step integer D(k) = c(k) - c_s (|D| < 2^24, exact in float32),
+//           N' = Q + D (2T + D) = fma(D, 2T + D, Q),
+//       one add and one fused multiply-add per row and term.  Per lane and
+//       row, T (int32) and Q (int64) are carried from split to split exactly
+//       (Q += D_s T; T += D_s; Q += D_s T, D_s = c(next split) - c_s) and
+//       rounded once to float32 there.  The error of N' is a few roundings of
+//       max(|Q|, |N'|), the size of N' itself over the split, instead of
+//       the size of t^2.
+//   EB: f1 = sig(sig+1) - c and f3 = c + mu are linear in c; per split the
+//       lane's first row splits T = sig(sig+1) - c_s and T3 = c_s + mu into
+//       float32 T_hi + T_lo exactly, so f1 = T_hi + (T_lo - D) and
+//       f3 = T3_hi + (D + T3_lo) round once; row j adds its exact integer
+//       offset (below 2^19) to those.
 // Accumulation, three levels per spectrum and lane-owned l1: kCompBlock
 // consecutive terms are summed with float32 FMA into a block sum; block sums
 // are added plainly into a mid sum; every kCompPeriod steps (and at the end of
@@ -380,7 +385,7 @@ constexpr int kCompBlock = 4 * kStripR;
 constexpr int kCompPeriod = 64;
 
 template <int R, int MODE>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave, MODE == kModePolEE ? 5 : 1)
 strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
     constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
     constexpr bool TE = MODE == kModePol;
@@ -412,29 +417,40 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     // Kahan pairs (sum, compensation) and mid sums per spectrum and lane-owned l1
     float kt[R], kte[R], kee[R], ct[R], cte[R], cee[R];
     float mt[R], mte[R], mee[R];
-    float gw[R], hw[R], beta[R];
-    // even L: gam = a + b - 1, beta = 2ab + 1; EB: gam = sig(sig+1), mu
+    float gw[R], hw[R];
+    // EB: gam = sig(sig+1), mu, and the exact offsets of rows j from the lane's first row
     int gam[R], mu[R];
-    // exact offsets of rows j from the lane's first row
     float dg[R], dm[R];
+    // even L, polarized: T = c_s - (a + b - 1) and Q = T^2 - (2ab + 1) at the current
+    // split start c_s, exact, and their float32 forms qf = fl(Q), rf = fl(2T)
+    int tq[R];
+    long long q64[R];
+    float qf[R], rf[R];
+    int c_cur = 0;
+    {
+        const int l3s = de + 2 * k_lo;
+        c_cur = l3s * (l3s + 1);
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         kt[j] = kte[j] = kee[j] = ct[j] = cte[j] = cee[j] = 0.0f;
         mt[j] = mte[j] = mee[j] = 0.0f;
+        qf[j] = rf[j] = 0.0f;
         const long long l1 = l1_0 + j, l2 = l1 + d;
         if (EB) {
             const long long sg = l1 + l2 + 1, tau = sg + 1;
             gam[j] = (int)(sg * (sg + 1));
             mu[j] = (int)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
-            beta[j] = 0.0f;
+            tq[j] = 0;
+            q64[j] = 0;
         } else {
             const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
-            gam[j] = (int)(aa + bb - 1);
-            mu[j] = 0;
-            beta[j] = (float)(2.0 * (double)aa * (double)bb + 1.0);
+            gam[j] = mu[j] = 0;
+            const long long t = (long long)c_cur - (aa + bb - 1);
+            tq[j] = (int)t;
+            q64[j] = t * t - (2 * aa * bb + 1);
         }
     }
-
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         dg[j] = (float)(gam[j] - gam[0]);
@@ -487,23 +503,37 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
-        float thi = 0.0f, tlo = 0.0f, t3hi = 0.0f, t3lo = 0.0f;   // first row's split
+        float thi = 0.0f, tlo = 0.0f, t3hi = 0.0f, t3lo = 0.0f;   // EB: first row's split
         const int kc_r = (kc + G - 1) / G * G;
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
         const float* ph = s_h + (R + 1) * lane + (R - 1);
         for (int sb = 0; sb < kc_r; sb += G) {
             if (sb % RB == 0) {
-                // even L: t = T + D(k), T = c(l3 at the split) - (a + b - 1) = T_hi + T_lo exactly.
-                // EB: f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c(l3 at the split), and
-                //     f3 = c + mu = T3 + D(k), T3 = c(l3 at the split) + mu, both split the same way.
                 const int l3c = de + 2 * (k0 + sb);
                 const int cc = l3c * (l3c + 1);
-                const int T = EB ? gam[0] - cc : cc - gam[0];
-                thi = (float)T;
-                tlo = (float)(T - (int)thi);
-                const int T3 = cc + mu[0];
-                t3hi = (float)T3;
-                t3lo = (float)(T3 - (int)t3hi);
+                if (EB) {
+                    // f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c_s, and
+                    // f3 = c + mu = T3 + D(k), T3 = c_s + mu, each split exactly into hi + lo
+                    const int T = gam[0] - cc;
+                    thi = (float)T;
+                    tlo = (float)(T - (int)thi);
+                    const int T3 = cc + mu[0];
+                    t3hi = (float)T3;
+                    t3lo = (float)(T3 - (int)t3hi);
+                } else if (POL) {
+                    // move (T, Q) from the previous split start to c_s = cc, exactly:
+                    // Q(c + D) = Q(c) + D (2T + D) = Q + D T + D (T + D)
+                    const int Ds = cc - c_cur;
+                    c_cur = cc;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        q64[j] += (long long)Ds * tq[j];
+                        tq[j] += Ds;
+                        q64[j] += (long long)Ds * tq[j];
+                        qf[j] = (float)(double)q64[j];
+                        rf[j] = 2.0f * (float)tq[j];
+                    }
+                }
             }
             float bt[R], bte[R], bee[R];
 #pragma unroll
@@ -521,8 +551,7 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                     for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
                     hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
                     const float4 uu = pu[u];
-                    // first row exact split; rows j > 0 add their exact integer offsets
-                    const float t0 = thi + (uu.w + tlo);
+                    // EB: first row exact split; rows j > 0 add their exact integer offsets
                     const float f10 = thi + (tlo - uu.w), f30 = t3hi + (uu.w + t3lo);
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
@@ -535,8 +564,8 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                         }
                         if (TTS) bt[j] = __builtin_fmaf(uu.x, P, bt[j]);
                         if (POL) {
-                            const float t = j == 0 ? t0 : t0 - dg[j];
-                            const float N = __builtin_fmaf(t, t, -beta[j]);
+                            // N' = Q + D (2T + D)
+                            const float N = __builtin_fmaf(uu.w, rf[j] + uu.w, qf[j]);
                             const float y = P * N;
                             if (TE) bte[j] = __builtin_fmaf(uu.y, y, bte[j]);
                             const float z = y * N;
