@@ -289,6 +289,26 @@ int couple_master_solve(couple_ctx *ctx, int pol, int n, const double *K, int n_
                         double *work, double *x, void *stream);
 
 /*
+ * couple_master_solve_noalloc -- couple_master_solve without the `work`
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * [m][m + n_rhs] workspace is a file-scope device array of
+ * COUPLE_NOALLOC_SOLVE_DOUBLES float64 (32 MiB) that every GPU the library
+ * runs on holds until the process ends; couple_init resolves its address on
+ * the context's device.  Arguments, layout, result and errors are those of
+ * couple_master_solve; in addition m * (m + n_rhs) must not exceed
+ * COUPLE_NOALLOC_SOLVE_DOUBLES (EINVAL otherwise, before any launch; with one
+ * right-hand side that is m <= 2047 unknowns).  The call allocates nothing and
+ * only enqueues the same kernel on `stream`.  All calls on one GPU share its
+ * array: calls that may overlap on one GPU (other streams, other threads or
+ * contexts) race and must be ordered by the caller.  Every entry the solve
+ * reads is written by the same launch first, so nothing needs clearing.
+ */
+#define COUPLE_NOALLOC_SOLVE_DOUBLES (1LL << 22)
+int couple_master_solve_noalloc(couple_ctx *ctx, int pol, int n, const double *K, int n_rhs,
+                                const double *rhs, double *x, void *stream);
+
+/*
  * couple_tables -- copy the context's look-up tables to HOST buffers (for
  * inspection and tests).  Any pointer may be NULL to skip that table.
  *   g    : lmax_max + 1 float64,   g[p] = g(p)                  (eq. gdef)

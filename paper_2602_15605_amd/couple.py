@@ -28,6 +28,7 @@ SPECTRUM_BITS = {"TT": TT, "TE": TE, "EE": EE, "BB": BB, "EB": EB}
 SPECTRUM_ORDER = ("TT", "TE", "EE", "BB", "EB")
 PRECISIONS = {"fp64": 0, "fp32c": 1, "mfma_fp32": 2, "mfma_bf16x3": 3}
 LMAX_LIMIT = 16384
+NOALLOC_SOLVE_DOUBLES = 1 << 22     # COUPLE_NOALLOC_SOLVE_DOUBLES: the static solve workspace (32 MiB)
 
 
 class CoupleError(RuntimeError):
@@ -80,6 +81,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_bin_spectra.restype = i
     lib.couple_master_solve.argtypes = [vp, i, i, dp, i, dp, dp, dp, vp]
     lib.couple_master_solve.restype = i
+    lib.couple_master_solve_noalloc.argtypes = [vp, i, i, dp, i, dp, dp, vp]
+    lib.couple_master_solve_noalloc.restype = i
     lib.couple_profile.argtypes = [vp, i]
     lib.couple_profile.restype = i
     lib.couple_profile_read.argtypes = [vp, vp, vp]
@@ -419,6 +422,34 @@ def couple_master_solve(ctx, K, rhs, pol=False, work=None, out=None, stream=None
     rc = load_library().couple_master_solve(ctx.handle, 1 if pol else 0, n, _dev_ptr(K, "K"), n_rhs,
                                             _dev_ptr(r2, "rhs"), _dev_ptr(work, "work"), _dev_ptr(out, "x"),
                                             _stream_handle(stream))
+    _check(rc, ctx)
+    return out.reshape(-1) if one else out
+
+
+def couple_master_solve_noalloc(ctx, K, rhs, pol=False, out=None, stream=None):
+    """couple_master_solve with the library's static device workspace instead of
+    ``work`` (no allocation in the C call; pass ``out`` to allocate nothing here
+    either).  Shapes as couple_master_solve; m * (m + n_rhs) <= NOALLOC_SOLVE_DOUBLES.
+    """
+    import torch
+    n = int(K.shape[-1])
+    m = 2 * n if pol else n
+    one = rhs.dim() == 1
+    r2 = rhs.reshape(1, -1) if one else rhs
+    if r2.shape[1] != m:
+        raise CoupleError(COUPLE_EINVAL, "rhs has %d entries per system, expected %d" % (r2.shape[1], m))
+    if not (K.is_contiguous() and r2.is_contiguous()):
+        raise CoupleError(COUPLE_EINVAL, "K and rhs must be contiguous")
+    n_rhs = int(r2.shape[0])
+    if K.numel() < (3 if pol else 1) * n * n:
+        raise CoupleError(COUPLE_EINVAL, "K holds %d entries, expected %d" % (K.numel(), (3 if pol else 1) * n * n))
+    if out is None:
+        out = torch.empty((n_rhs, m), dtype=torch.float64, device=K.device)
+    elif out.numel() < n_rhs * m:
+        raise CoupleError(COUPLE_EINVAL, "out holds %d entries, needs %d" % (out.numel(), n_rhs * m))
+    rc = load_library().couple_master_solve_noalloc(ctx.handle, 1 if pol else 0, n, _dev_ptr(K, "K"), n_rhs,
+                                                    _dev_ptr(r2, "rhs"), _dev_ptr(out, "x"),
+                                                    _stream_handle(stream))
     _check(rc, ctx)
     return out.reshape(-1) if one else out
 

@@ -232,6 +232,13 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
         release(c);
         return fail(nullptr, COUPLE_EDEVICE, "table build: %s", hipGetErrorString(e));
     }
+    // this device's copy of the couple_master_solve_noalloc workspace (device current)
+    e = couple::noalloc_scratch(c->device, &c->solve_scratch);
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, COUPLE_EDEVICE, "hipGetSymbolAddress of the solve workspace: %s",
+                    hipGetErrorString(e));
+    }
     *out_ctx = c;
     return COUPLE_OK;
 }
@@ -707,6 +714,34 @@ int couple_master_solve(couple_ctx* ctx, int pol, int n, const double* K, int n_
             return fail(ctx, COUPLE_EINVAL, "K, rhs, work and x must be 8-byte aligned");
     }
     hipError_t e = couple::launch_master_solve(pol, n, K, n_rhs, rhs, work, x, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "master_solve launch");
+    return COUPLE_OK;
+}
+
+int couple_master_solve_noalloc(couple_ctx* ctx, int pol, int n, const double* K, int n_rhs, const double* rhs,
+                                double* x, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    if (pol != 0 && pol != 1) return fail(ctx, COUPLE_EINVAL, "pol=%d: 0 (TT) or 1 (E/B block)", pol);
+    if (n < 1 || n_rhs < 1) return fail(ctx, COUPLE_EINVAL, "n=%d and n_rhs=%d must be >= 1", n, n_rhs);
+    const long long m = pol ? 2LL * n : n;
+    if (m + n_rhs > couple::kSolveMaxCols)
+        return fail(ctx, COUPLE_EINVAL, "%lld unknowns + %d right-hand sides exceed %d", m, n_rhs,
+                    couple::kSolveMaxCols);
+    if (m * (m + n_rhs) > couple::kNoallocSolveDoubles)
+        return fail(ctx, COUPLE_EINVAL,
+                    "the system needs %lld x %lld float64, more than the %lld of the static workspace "
+                    "(use couple_master_solve with a workspace)",
+                    m, m + n_rhs, couple::kNoallocSolveDoubles);
+    const double* ptrs[] = {K, rhs, x};
+    for (const double* p : ptrs) {
+        if (!p) return fail(ctx, COUPLE_EINVAL, "K, rhs and x must be non-NULL");
+        if (reinterpret_cast<uintptr_t>(p) % alignof(double))
+            return fail(ctx, COUPLE_EINVAL, "K, rhs and x must be 8-byte aligned");
+    }
+    if (!ctx->solve_scratch) return fail(ctx, COUPLE_EDEVICE, "the static solve workspace has no address");
+    hipError_t e = couple::launch_master_solve(pol, n, K, n_rhs, rhs, ctx->solve_scratch, x,
+                                               static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(ctx, e, "master_solve launch");
     return COUPLE_OK;
 }

@@ -44,6 +44,7 @@ struct couple_ctx {
     float* wpf = nullptr;        // float32 copies
     int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
     int* edges_host = nullptr;   // pinned staging for the bin edges
+    double* solve_scratch = nullptr;  // this device's copy of the no-alloc solve workspace
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
     // tile shape of the batched matrix-core kernels, [0] float32, [1] BF16x3
@@ -114,6 +115,11 @@ hipError_t launch_bin_spectra(const couple_ctx* ctx, int n_spec, const double* c
                               const int* bin_edges_host, int n_bins, double* out, hipStream_t s);
 hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const double* rhs, double* work,
                                double* x, hipStream_t s);
+// couple_master_solve_noalloc: the device address of this GPU's copy of the
+// file-scope workspace array (resolved once per device, with that device current).
+constexpr long long kNoallocSolveDoubles = COUPLE_NOALLOC_SOLVE_DOUBLES;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, double** ptr);
 
 // measurement hook: event marks around a kernel of stage `stage` (no-op unless profiling)
 void prof_begin(couple_ctx* ctx, hipStream_t s);

@@ -27,6 +27,8 @@
 // held in LDS: one wave per right-hand side solves the diagonal block (lanes
 // over its rows), then every thread updates rows above from U read straight
 // from memory.  A zero pivot (a singular system) gives NaN in every output.
+#include <mutex>
+
 #include "couple_internal.hpp"
 
 namespace couple {
@@ -380,6 +382,32 @@ hipError_t launch_bin_spectra(const couple_ctx* ctx, int n_spec, const double* c
     const int total = n_spec * n_bins;
     hipLaunchKernelGGL(bin_spectra_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// Workspace of couple_master_solve_noalloc: the [m][m + n_rhs] system lives in
+// this file-scope device array instead of a caller or library allocation.
+// Every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel: it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kNoallocSolveDoubles];
+
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(int device, double** ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        // called with `device` current: the symbol resolves to that GPU's copy
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const double* rhs, double* work,

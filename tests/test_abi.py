@@ -68,6 +68,7 @@ def test_host_side_argument_errors(lib):
     assert lib.couple_lmax_max(None) == -1
     assert lib.couple_bin_spectra(None, 1, None, 0, None, 1, None, None) == -1
     assert lib.couple_master_solve(None, 0, 1, None, 1, None, None, None, None) == -1
+    assert lib.couple_master_solve_noalloc(None, 0, 1, None, 1, None, None, None) == -1
     lib.couple_free(None)
 
 
@@ -97,3 +98,5 @@ def test_enum_values_match_the_binding():
     assert vals["COUPLE_FP32C"] == couple.PRECISIONS["fp32c"]
     assert vals["COUPLE_MFMA_FP32"] == couple.PRECISIONS["mfma_fp32"]
     assert vals["COUPLE_MFMA_BF16X3"] == couple.PRECISIONS["mfma_bf16x3"]
+    m = re.search(r"#define\s+COUPLE_NOALLOC_SOLVE_DOUBLES\s+\(1LL << (\d+)\)", open(HEADER).read())
+    assert m and (1 << int(m.group(1))) == couple.NOALLOC_SOLVE_DOUBLES
