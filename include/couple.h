@@ -91,14 +91,22 @@ enum couple_precision {
  * plus c_l = [(l-1) l (l+1) (l+2)]^{-1/2} (the 1/(lambda eta) factor of
  * App. B.3).  They are generated on the device by the g recurrence in
  * double-double arithmetic and rounded once to float64 and float32.
- * Workspace: 3 (lmax_max+1)(lmax_max+2)/2 float64 for the symmetric kernels
- * Xi plus 6 (2 lmax_max + 1) words for the scaled windows.
- * Errors: EINVAL (bad lmax_max, NULL ctx), ENOMEM, EDEVICE.
+ * Workspace: 4 (lmax_max+1)(lmax_max+2)/2 float64 for the symmetric kernels
+ * Xi (TT, TE, EE, EB) plus 6 (2 lmax_max + 1) words for the scaled windows.
+ * If the environment variable COUPLE_MAX_DEVICE_BYTES holds a positive decimal
+ * byte count, a context whose tables and workspace (and, later, batched
+ * workspace) would exceed it is refused with ENOMEM before any allocation.
+ * Errors: EINVAL (bad lmax_max, NULL ctx), ENOMEM (allocation failed, or the
+ * byte cap above), EDEVICE (no usable device, or a device error -- including
+ * one left by earlier work on the device, which HIP reports on the next call).
  */
 #define COUPLE_LMAX_LIMIT 16384
 int couple_init(int lmax_max, couple_ctx **ctx);
 
-/* couple_free -- release a context (NULL is a no-op).  Synchronises the device. */
+/* couple_free -- release a context (NULL is a no-op).  Synchronises the whole
+ * device first (hipDeviceSynchronize: work of other contexts and streams on it
+ * is waited for too), since the context does not track the streams its calls
+ * were enqueued on. */
 void couple_free(couple_ctx *ctx);
 
 /* couple_last_error -- NUL-terminated text of the last failure on ctx (owned
@@ -171,13 +179,15 @@ int couple_band_batched(couple_ctx *ctx, int n_masks, int l3_lo, int l3_hi, cons
  * couple_reserve_batched -- size the context's batched workspace for a batch
  * of n_masks windows with the given lmax (HOST array).  Allocates (this is the
  * one entry point besides couple_init that does); later batched calls of the
- * same or smaller size allocate nothing.  Synchronises the device when the
- * workspace grows.  Size: 3 (lmax_m+1)(lmax_m+2)/2 float64 per mask (its Xi),
+ * same or smaller size allocate nothing.  When the workspace grows it first
+ * synchronises the whole device (hipDeviceSynchronize, as couple_free), since
+ * earlier batched calls on any stream may still read the old workspace.
+ * Size: 3 (lmax_m+1)(lmax_m+2)/2 float64 per mask (its Xi),
  * plus, per group of 16 masks sorted by lmax (L = the group's largest), the
  * larger of the two W' tables: 3 (2L+33) x 16 float32 or
  * 3 x 2 x 2 x 16 x (L+64 rounded up to 8) bfloat16.
  * Errors: EINVAL (NULL ctx/lmax_i, n_masks outside [1, 64], lmax > lmax_max),
- * ENOMEM.
+ * ENOMEM (allocation failed, or above COUPLE_MAX_DEVICE_BYTES, see couple_init).
  */
 int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
 

@@ -3,6 +3,7 @@
 //   scale windows -> strip (l3 reduction on the upper triangle) -> fill or bin.
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -23,6 +24,17 @@ int fail(couple_ctx* ctx, int code, const char* fmt, ...) {
     else
         g_init_error = buf;
     return code;
+}
+
+// Optional cap on the device bytes one context may hold (tables, workspace and
+// batched workspace), from COUPLE_MAX_DEVICE_BYTES; 0 = no cap.  Checked on the
+// host before any allocation, so a request beyond it fails with ENOMEM.
+size_t device_byte_cap() {
+    const char* v = std::getenv("COUPLE_MAX_DEVICE_BYTES");
+    if (!v || !*v) return 0;
+    char* end = nullptr;
+    const unsigned long long n = std::strtoull(v, &end, 10);
+    return (end && *end == '\0') ? (size_t)n : 0;
 }
 
 int hip_fail(couple_ctx* ctx, hipError_t e, const char* what) {
@@ -195,11 +207,6 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
     couple_ctx* c = new (std::nothrow) couple_ctx();
     if (!c) return fail(nullptr, COUPLE_ENOMEM, "host allocation of the context failed");
     c->lmax_max = lmax_max;
-    hipError_t e = hipGetDevice(&c->device);
-    if (e != hipSuccess) {
-        release(c);
-        return fail(nullptr, COUPLE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
-    }
     const size_t pad = couple::kTablePad;
     const size_t ng = lmax_max + 1 + 2 * pad, nh = 2 * (size_t)lmax_max + 1 + 2 * pad;
     const size_t nw = 3 * (2 * (size_t)lmax_max + 1);
@@ -214,6 +221,20 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
         {(void**)&c->wp, nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
         {(void**)&c->edges_dev, (lmax_max + 2) * sizeof(int)},
     };
+    size_t total = 0;
+    for (auto& a : allocs) total += a.bytes;
+    const size_t cap = device_byte_cap();
+    if (cap && total > cap) {
+        release(c);
+        return fail(nullptr, COUPLE_ENOMEM, "lmax_max=%d needs %zu device bytes, above COUPLE_MAX_DEVICE_BYTES=%zu",
+                    lmax_max, total, cap);
+    }
+    c->dev_bytes = total;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        release(c);
+        return fail(nullptr, COUPLE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
     for (auto& a : allocs) {
         e = hipMalloc(a.p, a.bytes);
         if (e != hipSuccess) {
@@ -448,6 +469,12 @@ int couple_reserve_batched(couple_ctx* ctx, int n_masks, const int* lmax_i) {
     if (rc) return rc;
     const size_t need = couple::batched_workspace_bytes(p);
     if (need <= ctx->bws_bytes) return COUPLE_OK;
+    const size_t cap = device_byte_cap();
+    if (cap && ctx->dev_bytes + need > cap)
+        return fail(ctx, COUPLE_ENOMEM,
+                    "the batched workspace needs %zu device bytes; with the context's %zu that is above "
+                    "COUPLE_MAX_DEVICE_BYTES=%zu",
+                    need, ctx->dev_bytes, cap);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(ctx, e, "sync before workspace change");
     (void)hipFree(ctx->bws);

@@ -45,6 +45,7 @@ struct couple_ctx {
     int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
     int* edges_host = nullptr;   // pinned staging for the bin edges
     double* solve_scratch = nullptr;  // this device's copy of the no-alloc solve workspace
+    size_t dev_bytes = 0;        // device bytes of the tables and workspace above
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
     // tile shape of the batched matrix-core kernels, [0] float32, [1] BF16x3

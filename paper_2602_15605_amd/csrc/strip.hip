@@ -208,27 +208,31 @@ strip_fp64_kernel(StripArgs a) {
 
     for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
         const int kc = min(KC, k_hi - k0 + 1);
+        // steps are taken in groups of R; the staged U of steps kc .. kc_r - 1 is 0
+        const int kc_r = (kc + R - 1) / R * R;
         __syncthreads();
-        // stage g(e), e = A - k0 - KC + 1 + slot; h(e), e = A + d + k0 + slot
+        // stage g(e), e = A - k0 - KC + 1 + slot; h(e), e = A + d + k0 + slot.  The steps
+        // k0 .. k0 + kc_r - 1 read g slots KC - kc_r .. kLen - 1 and h slots 0 .. B + kc_r - 2.
         const int g_base = A - k0 - KC + 1;
         const int h_base = A + de + k0;
+        const int g_off = KC - kc_r, n_win = B + kc_r - 1;
         // the chunk's global loads in two batches (windows, then per-step factors)
         constexpr int NS = (W::kLen + kWave - 1) / kWave;
         constexpr int NU = KC / kWave;
         double gv[NS], hv[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            const int slot = lane + q * kWave;
-            const int eg = g_base + slot, eh = h_base + slot;
-            gv[q] = (slot < W::kLen && eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
-            hv[q] = (slot < W::kLen && eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
+            const int i = lane + q * kWave;
+            const int eg = g_base + g_off + i, eh = h_base + i;
+            gv[q] = (i < n_win && eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
+            hv[q] = (i < n_win && eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            const int slot = lane + q * kWave;
-            if (slot < W::kLen) {
-                s_g[W::phys(slot)] = gv[q];
-                s_h[W::phys(slot)] = hv[q];
+            const int i = lane + q * kWave;
+            if (i < n_win) {
+                s_g[W::phys(g_off + i)] = gv[q];
+                s_h[W::phys(i)] = hv[q];
             }
         }
         double ga[NU], gb[NU], w0[NU], w1[NU], w2[NU];
@@ -266,7 +270,7 @@ strip_fp64_kernel(StripArgs a) {
                     }
                 }
             }
-            s_u[s] = u;
+            if (s < kc_r) s_u[s] = u;
         }
         __syncthreads();
 
@@ -280,8 +284,6 @@ strip_fp64_kernel(StripArgs a) {
 #pragma unroll
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
-        // steps are taken in groups of R; the staged U of steps past kc is 0
-        const int kc_r = (kc + R - 1) / R * R;
         // phys(R lane + KC - 1 - s) and phys(R lane + R - 1 + s) for s = s0 + u:
         // per group of R steps the g pointer moves down and the h pointer up by R + 1
         const double* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
@@ -463,15 +465,20 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 
     for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
         const int kc = min(KC, k_hi - k0 + 1);
+        // steps run in blocks of G; the staged U of steps kc .. kc_r - 1 is 0
+        const int kc_r = (kc + G - 1) / G * G;
         __syncthreads();
         const int g_base = A - k0 - KC + 1;
         const int h_base = A + de + k0;
-        for (int slot = lane; slot < W::kLen; slot += kWave) {
-            const int eg = g_base + slot, eh = h_base + slot;
-            s_g[W::phys(slot)] = (eg >= 0 && eg < a.g_len) ? gf[eg] : 0.0f;
-            s_h[W::phys(slot)] = (eh >= 0 && eh < a.h_len) ? hf[eh] : 0.0f;
+        // the steps k0 .. k0 + kc_r - 1 read g slots KC - kc_r .. kLen - 1 and
+        // h slots 0 .. B + kc_r - 2: only those are staged
+        const int g_off = KC - kc_r;
+        for (int i = lane; i < B + kc_r - 1; i += kWave) {
+            const int eg = g_base + g_off + i, eh = h_base + i;
+            s_g[W::phys(g_off + i)] = (eg >= 0 && eg < a.g_len) ? gf[eg] : 0.0f;
+            s_h[W::phys(i)] = (eh >= 0 && eh < a.h_len) ? hf[eh] : 0.0f;
         }
-        for (int s = lane; s < KC; s += kWave) {
+        for (int s = lane; s < kc_r; s += kWave) {
             float4 u = {0.0f, 0.0f, 0.0f, 0.0f};
             if (s < kc) {
                 const int k = k0 + s;
@@ -504,7 +511,6 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
             for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
         }
         float thi = 0.0f, tlo = 0.0f, t3hi = 0.0f, t3lo = 0.0f;   // EB: first row's split
-        const int kc_r = (kc + G - 1) / G * G;
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
         const float* ph = s_h + (R + 1) * lane + (R - 1);
         for (int sb = 0; sb < kc_r; sb += G) {

@@ -100,3 +100,31 @@ def test_enum_values_match_the_binding():
     assert vals["COUPLE_MFMA_BF16X3"] == couple.PRECISIONS["mfma_bf16x3"]
     m = re.search(r"#define\s+COUPLE_NOALLOC_SOLVE_DOUBLES\s+\(1LL << (\d+)\)", open(HEADER).read())
     assert m and (1 << int(m.group(1))) == couple.NOALLOC_SOLVE_DOUBLES
+
+
+def test_device_byte_cap_gives_enomem(lib, monkeypatch):
+    """COUPLE_MAX_DEVICE_BYTES is checked on the host before any device call,
+    so a context above it is refused with ENOMEM (also on a machine without a
+    GPU)."""
+    from paper_2602_15605_amd import couple
+    monkeypatch.setenv("COUPLE_MAX_DEVICE_BYTES", "1000000")
+    h = ctypes.c_void_p()
+    assert lib.couple_init(2000, ctypes.byref(h)) == couple.COUPLE_ENOMEM
+    assert not h.value
+    msg = lib.couple_last_error(None).decode()
+    assert "COUPLE_MAX_DEVICE_BYTES" in msg and "lmax_max=2000" in msg
+
+
+def test_no_device_gives_edevice(lib, monkeypatch):
+    """Without a usable GPU, couple_init fails with EDEVICE and a message (the
+    device error path); on a GPU machine the context is simply released."""
+    from paper_2602_15605_amd import couple
+    monkeypatch.delenv("COUPLE_MAX_DEVICE_BYTES", raising=False)
+    h = ctypes.c_void_p()
+    rc = lib.couple_init(8, ctypes.byref(h))
+    if rc == couple.COUPLE_OK:
+        lib.couple_free(h)
+        pytest.skip("a GPU is visible here")
+    assert rc == couple.COUPLE_EDEVICE
+    assert not h.value
+    assert lib.couple_last_error(None).decode()

@@ -423,11 +423,13 @@ def test_lmax_limit_sampled_rows(torch_gpu, oracle_bulk, precision, tol):
         _say("lmax %d %s %s max rel err %.3e" % (lmax, precision, s, err))
 
 
-@pytest.mark.parametrize("n_bins", [512, 701])
+@pytest.mark.parametrize("n_bins", [512, 701, 4097])
 def test_unit_bins_equal_unbinned(torch_gpu, ctx, n_bins):
     """Bins one multipole wide reproduce the unbinned matrix bitwise, both for
     bin lists carried in the kernel arguments (<= 512 bins) and for longer lists
-    staged through the context's pinned buffer."""
+    staged through the context's pinned buffer.  4097 bins: 4097^2 bin pairs of
+    256 work-items exceed 2^32 work-items in one grid dimension, so the bin
+    kernel's grid is two-dimensional."""
     from paper_2602_15605_amd import couple
     lmax = n_bins - 1
     Ws = _windows(lmax, 91)
