@@ -268,6 +268,14 @@ def run_extras(torch, couple, synth, args):
     for prec in ("mfma_fp32", "mfma_bf16x3", "fp32c"):
         call = lambda: couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=prec, outs=outs)
         r = {"masks": len(lmaxes), "elements": n_el}
+        if prec == "mfma_bf16x3":
+            r["accuracy_class"] = "2e-5 (bfloat16 hi/lo split, bound 3*2^-16 per term); not a 1e-6 mode"
+        else:
+            r["accuracy_class"] = "1e-6"
+        if prec == "mfma_fp32":
+            # useful contraction FLOP (each mask at its own lmax); the kernel runs 4-mask
+            # tiles up to each tile's largest lmax, so at most three columns idle per tile
+            r["useful_contraction_flop"] = contraction
         if prec.startswith("mfma"):
             tm, fl, tms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2], outs=outs,
                                                          precision=prec)

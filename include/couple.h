@@ -77,7 +77,9 @@ enum couple_precision {
                               matrix cores with both operands split hi + lo and three
                               products (hi*hi + hi*lo + lo*hi) accumulated in float32;
                               relative error per term at most 3 * 2^-16 (4.6e-5),
-                              bfloat16 keeping 8 significant bits                */
+                              bfloat16 keeping 8 significant bits.  A 2e-5-class
+                              form (measured 1.4e-5 .. 2.0e-5): it does not meet
+                              the 1e-6 of COUPLE_FP32C and COUPLE_MFMA_FP32      */
 };
 
 /*
@@ -217,14 +219,21 @@ int couple_matrix_batched(couple_ctx *ctx, int n_masks, const int *lmax_i, const
 
 /*
  * Tile shape of a batched matrix-core kernel (precision COUPLE_MFMA_FP32 or
- * COUPLE_MFMA_BF16X3, each keeps its own): row_tiles 16-row tiles of one
- * diagonal per wavefront (1, 2 or 4) and the number of MFMA steps between
- * flushes of the float32 matrix-core accumulators into the running sums
- * (1..16; a float32 step covers 4 l3 values, a BF16x3 step 32).  Defaults:
- * float32 (2, 8), BF16x3 (2, 4).
+ * COUPLE_MFMA_BF16X3, each keeps its own), and how often the float32
+ * matrix-core accumulators are flushed into the running sums:
+ *   row_tiles 1, 2, 4: the 16-mask form -- masks sorted by lmax in column groups
+ *     of 16, each group run to its largest lmax; row_tiles 16-row tiles of one
+ *     diagonal per wavefront; flush = MFMA steps between flushes (1..16; a
+ *     float32 step covers 4 l3 values, a BF16x3 step 32).
+ *   row_tiles 64, 128 (COUPLE_MFMA_FP32 only): the 4-mask form -- every work
+ *     item runs tiles of four masks, each only as far as its largest lmax, on
+ *     4 x 4 x 1 blocks; row_tiles rows of one diagonal per wavefront; flush =
+ *     groups of 16 l3 values between flushes (1..4).
+ *   Defaults: float32 (2, 8), BF16x3 (2, 4).
  *
- * couple_autotune_batched times every row_tiles in {1,2,4} with flush in
- * {4,8} (float32) or {2,4} (BF16x3) on the given batch (same arguments as
+ * couple_autotune_batched times the candidate shapes -- float32: row_tiles
+ * 1, 2, 4 with flush 4 and 8, and 64, 128 with flush 2; BF16x3: row_tiles 1,
+ * 2, 4 with flush 2 and 4 -- on the given batch (same arguments as
  * couple_matrix_batched; out is overwritten), keeps the fastest in ctx for
  * later batched calls of that precision and returns it through the optional
  * HOST pointers.  Synchronises the stream.

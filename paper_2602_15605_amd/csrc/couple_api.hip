@@ -575,9 +575,15 @@ int couple_set_batched_tiles(couple_ctx* ctx, int precision, int row_tiles, int 
     int ti;
     int rc = tile_index(ctx, precision, &ti);
     if (rc) return rc;
-    if (row_tiles != 1 && row_tiles != 2 && row_tiles != 4)
-        return fail(ctx, COUPLE_EINVAL, "row_tiles=%d: must be 1, 2 or 4", row_tiles);
-    if (flush < 1 || flush > 16) return fail(ctx, COUPLE_EINVAL, "flush=%d outside [1, 16]", flush);
+    if (ti == 0 && (row_tiles == 64 || row_tiles == 128)) {
+        // the 4-mask form: flush in groups of 16 l3 steps
+        if (flush < 1 || flush > 4) return fail(ctx, COUPLE_EINVAL, "flush=%d outside [1, 4] (16-step groups)", flush);
+    } else {
+        if (row_tiles != 1 && row_tiles != 2 && row_tiles != 4)
+            return fail(ctx, COUPLE_EINVAL, "row_tiles=%d: must be 1, 2 or 4%s", row_tiles,
+                        ti == 0 ? " (16-mask form) or 64, 128 (4-mask form)" : "");
+        if (flush < 1 || flush > 16) return fail(ctx, COUPLE_EINVAL, "flush=%d outside [1, 16]", flush);
+    }
     ctx->batched_tm[ti] = row_tiles;
     ctx->batched_flush[ti] = flush;
     return COUPLE_OK;
@@ -603,9 +609,10 @@ int couple_autotune_batched(couple_ctx* ctx, int precision, int n_masks, const i
     int ti;
     int rc = tile_index(ctx, precision, &ti);
     if (rc) return rc;
-    static const int kTm[] = {1, 2, 4};
-    // flush candidates: float32 steps are 4 k, BF16x3 steps 32 k
-    static const int kFlush[2][2] = {{4, 8}, {2, 4}};
+    // (row_tiles, flush) candidates.  float32: the 16-mask form (flush every 16 or 32 l3)
+    // and the 4-mask form (flush every 32 l3); BF16x3: flush every 64 or 128 l3.
+    static const int kCand[2][8][2] = {{{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 4}, {4, 8}, {64, 2}, {128, 2}},
+                                       {{1, 2}, {1, 4}, {2, 2}, {2, 4}, {4, 2}, {4, 4}, {0, 0}, {0, 0}}};
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -615,31 +622,32 @@ int couple_autotune_batched(couple_ctx* ctx, int precision, int n_masks, const i
     const int tm0 = ctx->batched_tm[ti], fl0 = ctx->batched_flush[ti];
     float best = 3.4e38f;
     int btm = tm0, bfl = fl0;
-    for (int tm : kTm)
-        for (int fl : kFlush[ti]) {
-            ctx->batched_tm[ti] = tm;
-            ctx->batched_flush[ti] = fl;
-            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
-                                       stream);  // warm-up (and argument check)
-            if (rc) break;
-            (void)hipEventRecord(e0, s);
-            rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
-                                       stream);
-            (void)hipEventRecord(e1, s);
-            if (rc) break;
-            float ms = 0.0f;
-            hipError_t e = hipEventSynchronize(e1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                rc = hip_fail(ctx, e, "autotune timing");
-                break;
-            }
-            if (ms < best) {
-                best = ms;
-                btm = tm;
-                bfl = fl;
-            }
+    for (const auto& cand : kCand[ti]) {
+        const int tm = cand[0], fl = cand[1];
+        if (tm == 0) continue;
+        ctx->batched_tm[ti] = tm;
+        ctx->batched_flush[ti] = fl;
+        rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
+                                   stream);  // warm-up (and argument check)
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        rc = couple_matrix_batched(ctx, n_masks, lmax_i, W_TT, W_TP, W_PP, w_len_i, spectra, precision, out,
+                                   stream);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(ctx, e, "autotune timing");
+            break;
         }
+        if (ms < best) {
+            best = ms;
+            btm = tm;
+            bfl = fl;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {

@@ -23,8 +23,8 @@ struct BatchPlan {
     int lmax[kMaxGroups][kMaskGroup];
     const double* w[kMaxGroups][3][kMaskGroup];    // W_TT, W_TP, W_PP (NULL: unused)
     double* out[kMaxGroups][kMaskGroup];
-    int flush = 8;                                  // MFMA steps per accumulator flush
-    int tm = 2;                                     // 16-row tiles per wavefront (1, 2, 4)
+    int flush = 8;                                  // MFMA steps (4-mask form: 16-step groups) per flush
+    int tm = 2;                                     // 16-row tiles (1, 2, 4); float32 4-mask form: 64, 128 rows
 };
 
 }  // namespace couple
@@ -49,8 +49,8 @@ struct couple_ctx {
     void* bws = nullptr;         // batched workspace (couple_reserve_batched)
     size_t bws_bytes = 0;
     // tile shape of the batched matrix-core kernels, [0] float32, [1] BF16x3
-    int batched_flush[2] = {8, 4};   // MFMA steps per accumulator flush
-    int batched_tm[2] = {2, 2};      // 16-row tiles per wavefront
+    int batched_flush[2] = {8, 4};   // MFMA steps per flush (float32 4-mask form: 16-step groups)
+    int batched_tm[2] = {2, 2};      // 16-row tiles per wavefront (float32 4-mask form: 64 or 128 rows)
     std::string err;
     // measurement hook: event pairs recorded around each kernel
     bool profiling = false;

@@ -67,19 +67,21 @@ def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk, precision, tol):
     _say("batched small %s: max rel err %.3e" % (precision, worst))
 
 
-@pytest.mark.parametrize("precision,tol,flush", [("mfma_fp32", TOL_FP32C, 4), ("mfma_fp32", TOL_FP32C, 8),
-                                                  ("mfma_bf16x3", TOL_BF16X3, 4)])
-def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, tol, flush):
-    """The 32-mask workload at every flush interval the autotuner may pick."""
+@pytest.mark.parametrize("precision,tol,tm,flush", [("mfma_fp32", TOL_FP32C, 2, 4), ("mfma_fp32", TOL_FP32C, 2, 8),
+                                                     ("mfma_fp32", TOL_FP32C, 64, 2), ("mfma_fp32", TOL_FP32C, 128, 2),
+                                                     ("mfma_bf16x3", TOL_BF16X3, 2, 4)])
+def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, tol, tm, flush):
+    """The 32-mask workload in both float32 forms at every flush interval the
+    autotuner may pick."""
     from paper_2602_15605_amd import couple, synth
     torch = torch_gpu
     lmaxes = [int(x) for x in synth.batched_lmaxes()]
-    _say("workload3 batched %s flush %d" % (precision, flush))
+    _say("workload3 batched %s tiles %d flush %d" % (precision, tm, flush))
     Ws = [synth.workload_windows(3, mask=m) for m in range(len(lmaxes))]
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     couple.couple_reserve_batched(ctx, lmaxes)
     saved = couple.couple_get_batched_tiles(ctx, precision=precision)
-    couple.couple_set_batched_tiles(ctx, 2, flush, precision=precision)
+    couple.couple_set_batched_tiles(ctx, tm, flush, precision=precision)
     try:
         outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
         torch.cuda.synchronize()
@@ -92,7 +94,8 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, 
         Kr, Ar = oracle_bulk.coupling_rows(L, *Ws[m], rows=rows, spectra=SPEC4)
         for i, s in enumerate(SPEC4):
             worst[s] = max(worst[s], assert_parity(got[i], Kr[i], Ar[i], tol, "mask %d lmax %d %s" % (m, L, s)))
-    _say("workload3 batched %s flush %d max rel err: " % (precision, flush) + ", ".join("%s %.3e" % kv for kv in worst.items()))
+    _say("workload3 batched %s tiles %d flush %d max rel err: " % (precision, tm, flush)
+         + ", ".join("%s %.3e" % kv for kv in worst.items()))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
@@ -132,9 +135,13 @@ def test_batched_errors(torch_gpu, ctx):
         couple.couple_matrix(ctx, w[0], None, None, 40, spectra=("TT",), precision="mfma_bf16x3")
 
 
-@pytest.mark.parametrize("precision,tol,flushes", [("mfma_fp32", TOL_FP32C, (1, 4, 8, 16)),
-                                                    ("mfma_bf16x3", TOL_BF16X3, (1, 2, 4))])
-def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk, precision, tol, flushes):
+F32_SHAPES = [(tm, fl) for tm in (1, 2, 4) for fl in (1, 4, 8, 16)] + [(tm, fl) for tm in (64, 128) for fl in (1, 2, 4)]
+BF16_SHAPES = [(tm, fl) for tm in (1, 2, 4) for fl in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("precision,tol,shapes", [("mfma_fp32", TOL_FP32C, F32_SHAPES),
+                                                   ("mfma_bf16x3", TOL_BF16X3, BF16_SHAPES)])
+def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk, precision, tol, shapes):
     """Every tile shape gives a result within the bar; the autotuner keeps one of them."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
@@ -147,17 +154,16 @@ def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk, precision, tol, f
     other = "mfma_bf16x3" if precision == "mfma_fp32" else "mfma_fp32"
     saved_other = couple.couple_get_batched_tiles(ctx, precision=other)
     try:
-        for tm in (1, 2, 4):
-            for fl in flushes:
-                _say("%s row_tiles %d flush %d" % (precision, tm, fl))
-                couple.couple_set_batched_tiles(ctx, tm, fl, precision=precision)
-                outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision)
-                for m in range(len(lmaxes)):
-                    K = outs[m].cpu().numpy()
-                    for i, s in enumerate(SPEC4):
-                        assert_parity(K[i], refs[m][0][i], refs[m][1][i], tol, "tm %d flush %d %s" % (tm, fl, s))
+        for tm, fl in shapes:
+            _say("%s row_tiles %d flush %d" % (precision, tm, fl))
+            couple.couple_set_batched_tiles(ctx, tm, fl, precision=precision)
+            outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision)
+            for m in range(len(lmaxes)):
+                K = outs[m].cpu().numpy()
+                for i, s in enumerate(SPEC4):
+                    assert_parity(K[i], refs[m][0][i], refs[m][1][i], tol, "tm %d flush %d %s" % (tm, fl, s))
         tm, fl, ms = couple.couple_autotune_batched(ctx, lmaxes, dW[0], dW[1], dW[2], precision=precision)
-        assert tm in (1, 2, 4) and fl in flushes and ms > 0
+        assert (tm, fl) in shapes and ms > 0
         assert couple.couple_get_batched_tiles(ctx, precision=precision) == (tm, fl)
         assert couple.couple_get_batched_tiles(ctx, precision=other) == saved_other
         _say("autotune %s picked row_tiles=%d flush=%d (%.3f ms)" % (precision, tm, fl, ms))
