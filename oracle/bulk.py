@@ -52,6 +52,9 @@ def _load():
         lib.oracle_threej_row_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_void_p, ctypes.c_int]
         lib.oracle_threej_row_forward.restype = ctypes.c_int
+        lib.oracle_threej_row_m.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_threej_row_m.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -77,6 +80,16 @@ def threej_row_forward(l1: int, l2: int, m: int, l3_hi: int) -> np.ndarray:
     rc = _load().oracle_threej_row_forward(int(l1), int(l2), int(m), int(l3_hi), out.ctypes.data, n)
     if rc != n:
         raise RuntimeError("oracle_threej_row_forward failed (%d)" % rc)
+    return out
+
+
+def threej_row_m(l1: int, l2: int, m1: int, m2: int) -> np.ndarray:
+    """(l1 l2 l3; m1 m2 -m1-m2) for l3 = |l1-l2| .. l1+l2 (0 where l3 < |m1+m2|)."""
+    n = l1 + l2 - abs(l1 - l2) + 1
+    out = np.zeros(n, dtype=np.float64)
+    rc = _load().oracle_threej_row_m(int(l1), int(l2), int(m1), int(m2), out.ctypes.data, n)
+    if rc != n:
+        raise RuntimeError("oracle_threej_row_m failed (%d)" % rc)
     return out
 
 

@@ -378,6 +378,110 @@ int oracle_threej_row_forward(int l1, int l2, int m, int l3_hi, double *out, int
     return (int)n;
 }
 
+/* ------------------------------------------------------------------------
+ * Rows of (l1 l2 l3; m1 m2 m3) with any magnetic numbers, m3 = -m1 - m2 (the
+ * families of the Conclusion, e.g. (1 1 -2) and (2 2 -4), among others).
+ *
+ * The same Schulten--Gordon recursion, now with m3 != 0 in the first
+ * column: f(j) = (j l1 l2; m3 m1 m2), an even cyclic permutation of the
+ * symbol, and
+ *   j A(j+1) f(j+1) + B(j) f(j) + (j+1) A(j) f(j-1) = 0,
+ *   A(j) = sqrt[(j^2 - (l1-l2)^2)((l1+l2+1)^2 - j^2)(j^2 - m3^2)],
+ *   B(j) = -(2j+1)[(l1(l1+1) - l2(l2+1)) m3 - j(j+1)(m2 - m1)],
+ * over j = max(|l1-l2|, |m3|) .. l1+l2, where A vanishes at the lower end.
+ * It is run forward and backward and joined in the middle as in sg_row,
+ * normalised by sum_j (2j+1) f^2 = 1 (orthogonality at fixed m1, m2), and
+ * given the sign of the single-term Racah sum at the stretched end.  With
+ * m3 = 0 the rows of sg_row are used ((l1 l2 l3; m -m 0) with m = m1).
+ */
+static ld sg_a(long j, long d, long s, long m)
+{
+    ld a = (ld)j * (ld)j - (ld)d * (ld)d;
+    ld b = (ld)s * (ld)s - (ld)j * (ld)j;
+    ld c = (ld)j * (ld)j - (ld)m * (ld)m;
+    if (a <= 0 || b <= 0 || c <= 0) return 0.0L;
+    return sqrtl(a * b * c);
+}
+
+/* f[i] = (l1 l2 jlo+i; m1 m2 m3), i < n = l1+l2-jlo+1; fw, bw scratch of n. */
+static void sg_row_m(int l1, int l2, int m1, int m2, long jlo, long n, ld *f, ld *fw, ld *bw)
+{
+    const long m3 = -(long)m1 - m2;
+    const long d = (long)l1 - l2, s = (long)l1 + l2 + 1, jmax = (long)l1 + l2;
+    const ld kab = (ld)((long)l1 * (l1 + 1) - (long)l2 * (l2 + 1)) * (ld)m3;
+    const long im = (n - 1) / 2;
+    const long lo = im - 2 < 0 ? 0 : im - 2;
+    const long hi = im + 2 > n - 1 ? n - 1 : im + 2;
+    long i;
+    ld logabs = 0.0L;
+    int sign = 1;
+    for (i = 0; i < n; ++i) fw[i] = bw[i] = 0.0L;
+    /* forward from jlo: A(jlo) = 0 */
+    fw[0] = 1.0L;
+    for (i = 0; i < hi; ++i) {
+        const long j = jlo + i;
+        const ld b = -(ld)(2 * j + 1) * (kab - (ld)j * (ld)(j + 1) * (ld)(m2 - m1));
+        const ld back = i > 0 ? (ld)(j + 1) * sg_a(j, d, s, m3) * fw[i - 1] : 0.0L;
+        fw[i + 1] = -(b * fw[i] + back) / ((ld)j * sg_a(j + 1, d, s, m3));
+    }
+    /* backward from jmax: A(jmax + 1) = 0 */
+    bw[n - 1] = 1.0L;
+    for (i = n - 1; i > lo; --i) {
+        const long j = jlo + i;
+        const ld b = -(ld)(2 * j + 1) * (kab - (ld)j * (ld)(j + 1) * (ld)(m2 - m1));
+        const ld fwd = i + 1 < n ? (ld)j * sg_a(j + 1, d, s, m3) * bw[i + 1] : 0.0L;
+        bw[i - 1] = -(b * bw[i] + fwd) / ((ld)(j + 1) * sg_a(j, d, s, m3));
+    }
+    /* join: least-squares scale of bw onto fw over lo..hi */
+    {
+        ld num = 0.0L, den = 0.0L, scale;
+        for (i = lo; i <= hi; ++i) {
+            num += fw[i] * bw[i];
+            den += bw[i] * bw[i];
+        }
+        scale = num / den;
+        for (i = 0; i <= im; ++i) f[i] = fw[i];
+        for (i = im + 1; i < n; ++i) f[i] = scale * bw[i];
+    }
+    /* normalise and take the sign of the stretched end l3 = l1 + l2 */
+    {
+        ld norm = 0.0L;
+        for (i = 0; i < n; ++i) norm += (ld)(2 * (jlo + i) + 1) * f[i] * f[i];
+        norm = 1.0L / sqrtl(norm);
+        racah_single_term(l1, l2, jmax, m1, m2, m3, &logabs, &sign);
+        if ((ld)sign * f[n - 1] < 0) norm = -norm;
+        for (i = 0; i < n; ++i) f[i] *= norm;
+    }
+}
+
+/* (l1 l2 l3; m1 m2 -m1-m2) for l3 = |l1-l2| .. l1+l2 into out[0 .. n_out-1]
+ * (float64); entries with l3 < |m1 + m2| are 0, as is the whole row when
+ * |m1| > l1 or |m2| > l2.  Returns the row length. */
+int oracle_threej_row_m(int l1, int l2, int m1, int m2, double *out, int n_out)
+{
+    const long m3 = -(long)m1 - m2;
+    long n, jlo, i;
+    ld *buf;
+    if (l1 < 0 || l2 < 0 || !out) return -1;
+    n = (long)l1 + l2 - labs((long)l1 - l2) + 1;
+    if (n_out < n) return -1;
+    for (i = 0; i < n; ++i) out[i] = 0.0;
+    if (abs(m1) > l1 || abs(m2) > l2) return (int)n;
+    if (m3 == 0) return oracle_threej_row(l1, l2, m1, out, n_out);
+    jlo = labs((long)l1 - l2) > labs(m3) ? labs((long)l1 - l2) : labs(m3);
+    if (jlo > (long)l1 + l2) return (int)n;
+    buf = (ld *)malloc(sizeof(ld) * 3 * (size_t)(l1 + l2 - jlo + 1));
+    if (!buf) return -2;
+    {
+        const long nr = (long)l1 + l2 - jlo + 1;
+        const long off = jlo - labs((long)l1 - l2);
+        sg_row_m(l1, l2, m1, m2, jlo, nr, buf, buf + nr, buf + 2 * nr);
+        for (i = 0; i < nr; ++i) out[off + i] = (double)buf[i];
+    }
+    free(buf);
+    return (int)n;
+}
+
 /*
  * Band-limited K rows: as oracle_coupling_rows with the l3 sum restricted to
  * [l3_lo, l3_hi], but only the l2 with |l1 - l2| <= l3_hi are evaluated (the
