@@ -174,6 +174,13 @@ def run_context(torch, couple, synth):
         out["threej_rows_2000pairs_lmax6000_m%d" % m] = {
             "ms_per_call": ms, "symbols": n_sym, "symbols_per_s": n_sym / (ms * 1e-3),
             "note": "(l1 l2 l3; -m m 0) for every l3 of each pair, float64, rows padded to 12001"}
+    for (m1, m2) in ((1, 1), (2, 2)):
+        ms = _timed(torch, lambda: couple.couple_threej_rows_m(ctx, t1, t2, m1, m2, stride=2 * lmax + 1, out=rows),
+                    5, 2)
+        out["threej_rows_2000pairs_lmax6000_%d%d%d" % (m1, m2, -m1 - m2)] = {
+            "ms_per_call": ms, "symbols": n_sym, "symbols_per_s": n_sym / (ms * 1e-3),
+            "note": "(l1 l2 l3; %d %d %d) for every l3 of each pair, float64, exact 128-bit numerators" % (
+                m1, m2, -m1 - m2)}
     del rows
     out["master_solve_lmax6000_bins50"] = {
         "bins": nb, "tt_ms": ms_t, "eb_block_ms": ms_p,

@@ -270,6 +270,35 @@ int couple_threej_rows(couple_ctx *ctx, int m, int n_pairs, const int *l1, const
                        long long stride, void *stream);
 
 /*
+ * couple_threej_rows_m -- rows of Wigner 3j symbols (l1 l2 l3; m1 m2 m3),
+ * m3 = -m1 - m2, over every l3 = |l1-l2| .. l1+l2, for the small magnetic
+ * numbers whose two entries of equal sign (zero counts as either) are at most
+ * 2 in magnitude: the (1 1 -2) and (2 2 -4) families that the Conclusion
+ * names for the stochastic gravitational-wave background, their m-flips
+ * (-1 -1 2), (-2 -2 4) and column permutations such as (2 -1 -1), mixed
+ * ones such as (2 1 -3), and the (-m m 0), m <= 2, rows of couple_threej_rows.
+ * Each symbol is one table product in closed form: the App. B forms of the
+ * (0 -1 1) and (0 -2 2) families carried to (a b -a-b) by the lowering
+ * relation of E57 Sec. 3.7 and collapsed symbolically to
+ *   (x y z; a b -a-b) = T N_ab(x(x+1), y(y+1), z(z+1)) / (2 D_ab),
+ * T the (0 0 0) symbol of eq. 000_sq_main (even L) or its odd-L counterpart,
+ * N_ab an integer polynomial evaluated exactly, D_ab^2 a product of factorial
+ * ratios; so no cancellation, and no recursion along the row.  float64.
+ *   m1, m2   : the magnetic numbers of the l1 and l2 columns.
+ *   l1, l2   : DEVICE int32 arrays of n_pairs multipoles.  A pair outside
+ *              [0, lmax_max] gives a row of NaN (checked on the device).
+ *   out      : device float64 [n_pairs][stride]; out[p][i] is the symbol at
+ *              l3 = |l1-l2| + i for i < 2 min(l1, l2) + 1 and 0 beyond (also 0
+ *              where a selection rule |m| <= l fails); rows longer than stride
+ *              are cut at stride.
+ * Only enqueues one kernel (no allocation, graph-capturable).
+ * Errors: EINVAL (NULL ctx or pointer, misalignment, magnetic numbers outside
+ * the families above, n_pairs or stride out of range), EDEVICE.
+ */
+int couple_threej_rows_m(couple_ctx *ctx, int m1, int m2, int n_pairs, const int *l1, const int *l2, double *out,
+                         long long stride, void *stream);
+
+/*
  * Binned MASTER solve (Sec. 2, eq. pseudo_cl).  The pseudo-spectra are linear
  * in the true spectra,
  *   <C~^TT> = K^TT C^TT,

@@ -10,7 +10,7 @@ Function names follow the C ABI: ``couple_init``, ``couple_free``,
 ``couple_last_error``, ``couple_matrix``, ``couple_band``,
 ``couple_band_batched``, ``couple_matrix_batched`` (with ``couple_reserve_batched``,
 the tile setters and ``couple_autotune_batched``), ``couple_bin_spectra``,
-``couple_master_solve``, ``couple_threej_rows``, ``couple_tables`` and the
+``couple_master_solve``, ``couple_threej_rows``, ``couple_threej_rows_m``, ``couple_tables`` and the
 profiling hooks.  ``xi=True`` sets the COUPLE_XI output flag.
 """
 import ctypes
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.couple_tables.restype = i
     lib.couple_threej_rows.argtypes = [vp, i, i, vp, vp, dp, ctypes.c_longlong, vp]
     lib.couple_threej_rows.restype = i
+    lib.couple_threej_rows_m.argtypes = [vp, i, i, i, vp, vp, dp, ctypes.c_longlong, vp]
+    lib.couple_threej_rows_m.restype = i
     lib.couple_bin_spectra.argtypes = [vp, i, dp, i, vp, i, dp, vp]
     lib.couple_bin_spectra.restype = i
     lib.couple_master_solve.argtypes = [vp, i, i, dp, i, dp, dp, dp, vp]
@@ -347,6 +349,27 @@ def couple_threej_rows(ctx, l1, l2, m, stride=None, out=None, stream=None):
     l3 = |l1[p]-l2[p]| on, 0 past the row's end.  ``stride`` defaults to the
     longest row, 2 max(min(l1, l2)) + 1.
     """
+    t1, t2, n, stride, out = _rows_args(l1, l2, stride, out)
+    rc = load_library().couple_threej_rows(ctx.handle, int(m), n, t1.data_ptr(), t2.data_ptr(), _dev_ptr(out, "out"),
+                                           int(stride), _stream_handle(stream))
+    _check(rc, ctx)
+    return out
+
+
+def couple_threej_rows_m(ctx, l1, l2, m1, m2, stride=None, out=None, stream=None):
+    """Rows of (l1 l2 l3; m1 m2 -m1-m2) for l3 = |l1-l2| .. l1+l2, for the
+    small-m families (e.g. (1 1 -2), (2 2 -4), their m-flips and permutations).
+
+    Arguments, layout and return value as ``couple_threej_rows``.
+    """
+    t1, t2, n, stride, out = _rows_args(l1, l2, stride, out)
+    rc = load_library().couple_threej_rows_m(ctx.handle, int(m1), int(m2), n, t1.data_ptr(), t2.data_ptr(),
+                                             _dev_ptr(out, "out"), int(stride), _stream_handle(stream))
+    _check(rc, ctx)
+    return out
+
+
+def _rows_args(l1, l2, stride, out):
     import torch
     dev = torch.device("cuda")
     t1 = l1 if isinstance(l1, torch.Tensor) else torch.as_tensor(np.asarray(l1, dtype=np.int32))
@@ -362,10 +385,7 @@ def couple_threej_rows(ctx, l1, l2, m, stride=None, out=None, stream=None):
         out = torch.empty((n, int(stride)), dtype=torch.float64, device=dev)
     elif out.numel() < n * int(stride):
         raise CoupleError(COUPLE_EINVAL, "out holds %d entries, needs %d" % (out.numel(), n * int(stride)))
-    rc = load_library().couple_threej_rows(ctx.handle, int(m), n, t1.data_ptr(), t2.data_ptr(), _dev_ptr(out, "out"),
-                                           int(stride), _stream_handle(stream))
-    _check(rc, ctx)
-    return out
+    return t1, t2, n, int(stride), out
 
 
 def couple_bin_spectra(ctx, cl, bin_edges, out=None, stream=None):

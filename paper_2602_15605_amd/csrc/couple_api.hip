@@ -801,4 +801,36 @@ int couple_threej_rows(couple_ctx* ctx, int m, int n_pairs, const int* l1, const
     return COUPLE_OK;
 }
 
+int couple_threej_rows_m(couple_ctx* ctx, int m1, int m2, int n_pairs, const int* l1, const int* l2, double* out,
+                         long long stride, void* stream) {
+    if (!ctx) return COUPLE_EINVAL;
+    ctx->err.clear();
+    // canonical form: rotate the columns until the first two magnetic numbers
+    // share a sign, flip them to >= 0 if needed; both must then be <= 2
+    const long long ms[3] = {m1, m2, -(long long)m1 - m2};
+    int rot = -1, flip = 0, fa = 0, fb = 0;
+    for (int r = 0; r < 3 && rot < 0; ++r) {
+        const long long p = ms[r], q = ms[(r + 1) % 3];
+        if (p >= 0 && q >= 0 && p <= 2 && q <= 2) {
+            rot = r, flip = 0, fa = (int)p, fb = (int)q;
+        } else if (p <= 0 && q <= 0 && p >= -2 && q >= -2) {
+            rot = r, flip = 1, fa = (int)-p, fb = (int)-q;
+        }
+    }
+    if (rot < 0)
+        return fail(ctx, COUPLE_EINVAL,
+                    "(m1, m2, m3) = (%d, %d, %lld): the two entries of equal sign must be at most 2 in magnitude", m1,
+                    m2, ms[2]);
+    if (n_pairs < 1) return fail(ctx, COUPLE_EINVAL, "n_pairs=%d < 1", n_pairs);
+    if (stride < 1) return fail(ctx, COUPLE_EINVAL, "stride=%lld < 1", stride);
+    if (!l1 || !l2 || !out) return fail(ctx, COUPLE_EINVAL, "l1, l2 and out must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(l1) % alignof(int) || reinterpret_cast<uintptr_t>(l2) % alignof(int) ||
+        reinterpret_cast<uintptr_t>(out) % alignof(double))
+        return fail(ctx, COUPLE_EINVAL, "l1, l2 (4 bytes) or out (8 bytes) misaligned");
+    hipError_t e = couple::launch_threej_family(ctx, rot, flip, fa, fb, n_pairs, l1, l2, out, stride,
+                                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "threej_rows_m launch");
+    return COUPLE_OK;
+}
+
 }  // extern "C"

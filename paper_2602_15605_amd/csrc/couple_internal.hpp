@@ -109,6 +109,10 @@ hipError_t launch_zero(double* out, size_t n, hipStream_t s);
 // rows of 3j symbols (l1 l2 l3; -m m 0) from the tables (threej.hip)
 hipError_t launch_threej_rows(const couple_ctx* ctx, int m, int n_pairs, const int* l1, const int* l2, double* out,
                               long long stride, hipStream_t s);
+// rows of (l1 l2 l3; m1 m2 m3) in the canonical form (x y z; a b -a-b),
+// 0 <= a, b <= 2, (x, y, z) = (l1, l2, l3) rotated left by rot, times (-1)^L if flip
+hipError_t launch_threej_family(const couple_ctx* ctx, int rot, int flip, int a, int b, int n_pairs, const int* l1,
+                                const int* l2, double* out, long long stride, hipStream_t s);
 
 // binned MASTER solve (solve.hip)
 constexpr int kSolveMaxCols = 4096;    // unknowns + right-hand sides of one solve
