@@ -185,6 +185,31 @@ def run_context(torch, couple, synth):
     out["master_solve_lmax6000_bins50"] = {
         "bins": nb, "tt_ms": ms_t, "eb_block_ms": ms_p,
         "note": "binned pseudo-spectra + LU solve on one work-group; TT is %d unknowns, E/B %d" % (nb, 2 * nb)}
+    # fine bins (width 3): TT 2000 unknowns, E/B 4000, on the multi-work-group path
+    edges3 = list(range(2, lmax + 2, 3))
+    if edges3[-1] != lmax + 1:
+        edges3.append(lmax + 1)
+    nb3 = len(edges3) - 1
+    Kt3 = couple.couple_band(ctx, 0, 2 * lmax, dW[0], None, None, lmax, spectra=("TT",), precision="fp32c",
+                             bin_edges=edges3)[0].contiguous()
+    Kp3 = couple.couple_band(ctx, 0, 2 * lmax, None, None, dW[2], lmax, spectra=("EE", "BB", "EB"),
+                             precision="fp32c", bin_edges=edges3)
+    # right-hand sides of C_b = 1 in every bin: the row sums of the binned systems
+    rt3 = Kt3.sum(dim=1).reshape(1, -1).contiguous()
+    rp3 = torch.cat([Kp3[0].sum(dim=1) + Kp3[2].sum(dim=1), Kp3[2].sum(dim=1) + Kp3[1].sum(dim=1)]).reshape(1, -1)
+    wt3 = torch.empty(nb3 * (nb3 + 1), dtype=torch.float64, device="cuda")
+    wp3 = torch.empty(2 * nb3 * (2 * nb3 + 1), dtype=torch.float64, device="cuda")
+    xt3 = torch.empty((1, nb3), dtype=torch.float64, device="cuda")
+    xp3 = torch.empty((1, 2 * nb3), dtype=torch.float64, device="cuda")
+    ms_t3 = _timed(torch, lambda: couple.couple_master_solve(ctx, Kt3, rt3, work=wt3, out=xt3), 3, 1)
+    ms_p3 = _timed(torch, lambda: couple.couple_master_solve(ctx, Kp3, rp3.contiguous(), pol=True, work=wp3,
+                                                             out=xp3), 3, 1)
+    out["master_solve_lmax6000_bins3"] = {
+        "bins": nb3, "tt_ms": ms_t3, "eb_block_ms": ms_p3,
+        "max_abs_dev_from_1": {"tt": float((xt3 - 1.0).abs().max()), "eb": float((xp3 - 1.0).abs().max())},
+        "note": "the solve alone, right-hand sides K 1, so C_b = 1 comes back; TT is %d unknowns, E/B %d, "
+                "outer panels spread over the chip" % (nb3, 2 * nb3)}
+    del Kt3, Kp3, wp3
     couple.couple_free(ctx)
     return out
 

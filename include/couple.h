@@ -325,9 +325,13 @@ int couple_threej_rows_m(couple_ctx *ctx, int m1, int m2, int n_pairs, const int
  *   work : device float64 workspace of m * (m + n_rhs) entries, overwritten.
  *   x    : device float64 [n_rhs][m], the solution.
  *   m + n_rhs <= 4096.  Gaussian elimination with partial pivoting in
- *   float64 on one work-group; K and rhs are not modified.  A singular system
- *   (a zero pivot column) gives NaN in every entry of x.  Only enqueues one
- *   kernel (no allocation, graph-capturable).
+ *   float64; K and rhs are not modified.  Below 400 unknowns one work-group
+ *   runs it all (one kernel).  From 400 on, outer panels of 32 columns are
+ *   factorised by one work-group each while the row exchanges, U12 and the
+ *   trailing updates are spread over the chip (3 kernels per panel); x serves
+ *   as the scratch for each panel's pivots until the back substitution
+ *   writes it.  A singular system (a zero pivot column) gives NaN in every
+ *   entry of x.  Only enqueues kernels (no allocation, graph-capturable).
  * Errors (both): EINVAL (NULL ctx or pointer, misaligned pointer, sizes or
  * edges out of range), EDEVICE.
  */
@@ -347,10 +351,10 @@ int couple_master_solve(couple_ctx *ctx, int pol, int n, const double *K, int n_
  * couple_master_solve; in addition m * (m + n_rhs) must not exceed
  * COUPLE_NOALLOC_SOLVE_DOUBLES (EINVAL otherwise, before any launch; with one
  * right-hand side that is m <= 2047 unknowns).  The call allocates nothing and
- * only enqueues the same kernel on `stream`.  All calls on one GPU share its
+ * only enqueues the same kernels on `stream`.  All calls on one GPU share its
  * array: calls that may overlap on one GPU (other streams, other threads or
  * contexts) race and must be ordered by the caller.  Every entry the solve
- * reads is written by the same launch first, so nothing needs clearing.
+ * reads is written earlier in the same call, so nothing needs clearing.
  */
 #define COUPLE_NOALLOC_SOLVE_DOUBLES (1LL << 22)
 int couple_master_solve_noalloc(couple_ctx *ctx, int pol, int n, const double *K, int n_rhs,

@@ -9,24 +9,43 @@
 // K_{b b'} C_{b'} = C~_b, C~_b = (1/n_b) sum_{l in b} C~_l.
 //
 // bin_spectra_kernel: one thread per (spectrum, bin), the bin's sum in l order.
-// master_solve_kernel: one work-group assembles [K | C~] (TT, or the 2 x 2
-// block system for E/B) in the caller's workspace and runs a blocked LU with
-// partial pivoting (largest |pivot|, the first row on ties):
-//   * a panel of NB columns (8, or 4 when the rows would not fit) is
-//     factorised in LDS: by one wave, with no work-group barrier per column,
-//     when it has at most kWavePanelRows rows, else by every wave; the
-//     pivot's arg-max over a wave runs on DPP lane moves;
+//
+// The solve is Gaussian elimination with partial pivoting (largest |pivot|,
+// the first row on ties) on the augmented matrix [K | C~] (TT, or the 2 x 2
+// block system for E/B) in the caller's workspace, then back substitution.
+// Panels are factorised in LDS by one work-group:
+//   * a panel of NB columns (8, or 4 when its rows would not fit) by one wave,
+//     with no work-group barrier per column, when it has at most
+//     kWavePanelRows rows, else by every wave; the pivot's arg-max over a wave
+//     runs on DPP lane moves;
 //   * right of the panel, each column applies the panel's row exchanges and
 //     the unit-lower forward substitution U12 = L11^-1 A12;
 //   * the trailing block gets A22 -= L21 U12: lanes over 64 consecutive
 //     columns (U12 in registers), the waves split over (column chunk, row
-//     group) tasks, and each lane loads 8 rows before it stores any, so A is
-//     read once per panel with several loads in flight.
-// Then the right-hand sides (columns m .. of the augmented matrix) are back-
-// substituted in blocks of kBackBlock rows from the bottom, a chunk of them
-// held in LDS: one wave per right-hand side solves the diagonal block (lanes
-// over its rows), then every thread updates rows above from U read straight
-// from memory.  A zero pivot (a singular system) gives NaN in every output.
+//     group) tasks, and each lane loads 8 rows before it stores any.
+// Small systems (m < kMultiMin) run all of it in one work-group
+// (master_solve_kernel).  Larger ones split the matrix into outer panels of
+// kOuterNB columns and spread the O(m^3) part over the chip:
+//   solve_assemble_kernel     [K | C~] into the workspace, one work-group per row;
+//   solve_panel_kernel        one work-group factorises the outer panel (rows
+//                             k0 .. m-1) in inner panels of NB columns as above,
+//                             keeping the row exchanges of the panel's earlier
+//                             columns (the L21 the update reads) in step;
+//   solve_swap_trsm_kernel    right of the outer panel, 64 columns per
+//                             work-group: the panel's row exchanges, composed
+//                             into one permutation of the touched rows and
+//                             applied through LDS, then U12 = L11^-1 A12;
+//   solve_update_kernel       A22 -= L21 U12 in 64 x 64 tiles (4 x 4 per
+//                             thread, the depth-64 operands staged in LDS);
+//   solve_back_kernel         back substitution (one work-group).
+// The panel's pivots travel from the panel kernel to the swap kernel in the
+// first kOuterNB entries of x, and x[kOuterNB] is a singular flag that every
+// later kernel reads first; back substitution overwrites all of x last.
+// Back substitution: the right-hand sides (columns m .. of the augmented
+// matrix) in blocks of kBackBlock rows from the bottom, a chunk of them held in
+// LDS: one wave per right-hand side solves the diagonal block (lanes over its
+// rows), then every thread updates rows above from U read straight from memory.
+// A zero pivot (a singular system) gives NaN in every output.
 #include <mutex>
 
 #include "couple_internal.hpp"
@@ -113,100 +132,93 @@ constexpr int kRowBatch = 8;      // rows of the trailing update loaded before a
 constexpr int kWavePanelRows = 512;  // panels up to this many rows are factorised by one wave
 constexpr int kBackBlock = 64;    // rows per diagonal block of the back substitution
 
+// The work-group's LDS for factorising one panel.
 template <int NB>
-__global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a) {
-    __shared__ double s_panel[kPanelDoubles];    // [row - k0][NB]
-    __shared__ int s_perm[NB];                   // row exchanges of the panel (panel rows)
-    __shared__ int s_sing;                       // the panel met a zero pivot
-    __shared__ double s_cv[kSolveWaves];         // per-wave pivot candidates (tall panels)
-    __shared__ int s_ci[kSolveWaves];
-    __shared__ double s_pv;                      // chosen pivot magnitude and panel row
-    __shared__ int s_pi;
-    const int t = threadIdx.x;
-    const int lane = t % kWave, wave = t / kWave;
-    const int n = a.n, m = a.m, nr = a.n_rhs;
-    const long long ld = (long long)m + nr;
-    double* A = a.work;
+struct PanelLds {
+    double panel[kPanelDoubles];     // [row - k0][NB]
+    int perm[NB];                    // row exchanges of the panel (panel rows)
+    int sing;                        // the panel met a zero pivot
+    double cv[kSolveWaves];          // per-wave pivot candidates (tall panels)
+    int ci[kSolveWaves];
+    double pv;                       // chosen pivot magnitude and panel row
+    int pi;
+    int trow[2 * NB];                // rows the exchanges touch (panel-relative): the panel's top first
+    int tsrc[2 * NB];                // the row whose old values land in trow[i]
+    int tn;
+};
 
-    // assemble [K | C~]
-    for (int r = wave; r < m; r += kSolveWaves) {
-        for (int c = lane; c < (int)ld; c += kWave) {
-            double v;
-            if (c >= m) {
-                v = a.rhs[(long long)(c - m) * m + r];
-            } else if (!a.pol) {
-                v = a.K[(long long)r * n + c];
-            } else {
-                const int br = r / n, bc = c / n;
-                const int blk = br != bc ? 2 : br;    // [EE EB; EB BB]
-                v = a.K[((long long)blk * n + (r - br * n)) * n + (c - bc * n)];
-            }
-            A[r * ld + c] = v;
+// Compose the panel's exchanges (row j <-> perm[j], in order) into one
+// permutation of the rows they touch: after all of them, row trow[i] holds
+// what row tsrc[i] held before.  One thread; at most 2 NB rows.
+template <int NB>
+__device__ inline void compose_exchanges(PanelLds<NB>& L, int nb) {
+    int n = nb;
+    for (int j = 0; j < nb; ++j) L.trow[j] = L.tsrc[j] = j;
+    for (int j = 0; j < nb; ++j) {
+        const int p = L.perm[j];
+        if (p == j) continue;
+        int ip = -1;
+        for (int i = 0; i < n; ++i)
+            if (L.trow[i] == p) ip = i;
+        if (ip < 0) {
+            ip = n++;
+            L.trow[ip] = L.tsrc[ip] = p;
+        }
+        const int tmp = L.tsrc[j];
+        L.tsrc[j] = L.tsrc[ip];
+        L.tsrc[ip] = tmp;
+    }
+    L.tn = n;
+}
+
+// Rows k0 .. k0+mr-1, columns k0 .. k0+nb-1 of A into L.panel (columns nb ..
+// NB-1 zero).  Each thread issues kLoadBatch loads before it stores any.
+constexpr int kLoadBatch = 8;
+template <int NB>
+__device__ inline void load_panel(PanelLds<NB>& L, const double* A, long long ld, int k0, int mr, int nb) {
+    const int total = mr * NB;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kSolveThreads * kLoadBatch) {
+        double v[kLoadBatch];
+#pragma unroll
+        for (int q = 0; q < kLoadBatch; ++q) {
+            const int e = e0 + q * kSolveThreads;
+            const int r = e / NB, j = e - r * NB;
+            v[q] = (e < total && j < nb) ? A[(k0 + r) * ld + k0 + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kLoadBatch; ++q) {
+            const int e = e0 + q * kSolveThreads;
+            if (e < total) L.panel[e] = v[q];
         }
     }
-    __syncthreads();
+}
 
-    bool singular = false;
-    for (int k0 = 0; k0 < m; k0 += NB) {
-        const int nb = min(NB, m - k0);
-        const int mr = m - k0;
-        // panel: rows k0 .. m-1, columns k0 .. k0+nb-1
-        for (int e = t; e < mr * NB; e += kSolveThreads) {
-            const int r = e / NB, j = e - r * NB;
-            s_panel[e] = j < nb ? A[(k0 + r) * ld + k0 + j] : 0.0;
-        }
-        __syncthreads();
-        if (mr <= kWavePanelRows) {
-            // short panel: one wave, no work-group barrier per column
-            if (wave == 0) {
-                bool sing = false;
-                for (int j = 0; j < nb; ++j) {
-                    double best = -1.0;
-                    int bi = mr;
-                    for (int r = j + lane; r < mr; r += kWave) {
-                        const double v = fabs(s_panel[r * NB + j]);
-                        if (v > best) {
-                            best = v;
-                            bi = r;
-                        }
-                    }
-                    wave_argmax(best, bi);
-                    if (!(best > 0.0)) {         // zero (or NaN) pivot column: the system is singular
-                        sing = true;
-                        break;
-                    }
-                    bi = min(max(bi, j), mr - 1);    // a candidate row of this column
-                    if (lane < NB && bi != j) {
-                        const double x = s_panel[j * NB + lane];
-                        s_panel[j * NB + lane] = s_panel[bi * NB + lane];
-                        s_panel[bi * NB + lane] = x;
-                    }
-                    if (lane == 0) s_perm[j] = bi;
-                    // the exchanged rows are read by other lanes of this wave
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    // multipliers of column j and the rank-1 update of the panel's later columns
-                    const double piv = s_panel[j * NB + j];
-                    for (int r = j + 1 + lane; r < mr; r += kWave) {
-                        const double l = s_panel[r * NB + j] / piv;
-                        s_panel[r * NB + j] = l;
-#pragma unroll
-                        for (int cc = 0; cc < NB; ++cc)
-                            if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                }
-                if (lane == 0) s_sing = sing ? 1 : 0;
-            }
-            __syncthreads();
-            singular = s_sing != 0;
-        } else {
-            // tall panel: every wave scans rows; four work-group barriers per column
+// Entry (r, c) of the augmented matrix [K | C~]: TT, or [EE EB; EB BB] for E/B.
+__device__ inline double assembled(const SolveArgs& a, int r, int c) {
+    if (c >= a.m) return a.rhs[(long long)(c - a.m) * a.m + r];
+    if (!a.pol) return a.K[(long long)r * a.n + c];
+    const int n = a.n, br = r / n, bc = c / n;
+    const int blk = br != bc ? 2 : br;
+    return a.K[((long long)blk * n + (r - br * n)) * n + (c - bc * n)];
+}
+
+// Factorise the mr x nb panel in L.panel with partial pivoting: multipliers
+// below the diagonal, U11 on and above it, the exchanges in L.perm.  Called by
+// every thread of the work-group; returns true (in every thread) on a zero or
+// NaN pivot column.
+template <int NB>
+__device__ bool factor_panel(PanelLds<NB>& L, int mr, int nb) {
+    const int t = threadIdx.x;
+    const int lane = t % kWave, wave = t / kWave;
+    double* s_panel = L.panel;
+    if (mr <= kWavePanelRows) {
+        // short panel: one wave, no work-group barrier per column
+        if (wave == 0) {
+            bool sing = false;
             for (int j = 0; j < nb; ++j) {
                 double best = -1.0;
                 int bi = mr;
-                for (int r = j + t; r < mr; r += kSolveThreads) {
+                for (int r = j + lane; r < mr; r += kWave) {
                     const double v = fabs(s_panel[r * NB + j]);
                     if (v > best) {
                         best = v;
@@ -214,115 +226,191 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
                     }
                 }
                 wave_argmax(best, bi);
-                if (lane == 0) {
-                    s_cv[wave] = best;
-                    s_ci[wave] = bi;
-                }
-                __syncthreads();
-                if (wave == 0) {
-                    double v = lane < kSolveWaves ? s_cv[lane] : -1.0;
-                    int idx = lane < kSolveWaves ? s_ci[lane] : mr;
-                    wave_argmax(v, idx);
-                    if (lane == 0) {
-                        s_pv = v;
-                        s_pi = idx;
-                    }
-                }
-                __syncthreads();
-                if (!(s_pv > 0.0)) {             // zero (or NaN) pivot column: the system is singular
-                    singular = true;
+                if (!(best > 0.0)) {         // zero (or NaN) pivot column: the system is singular
+                    sing = true;
                     break;
                 }
-                const int p = min(max(s_pi, j), mr - 1);    // a candidate row of this column
-                if (t < NB && p != j) {
-                    const double x = s_panel[j * NB + t];
-                    s_panel[j * NB + t] = s_panel[p * NB + t];
-                    s_panel[p * NB + t] = x;
+                bi = min(max(bi, j), mr - 1);    // a candidate row of this column
+                if (lane < NB && bi != j) {
+                    const double x = s_panel[j * NB + lane];
+                    s_panel[j * NB + lane] = s_panel[bi * NB + lane];
+                    s_panel[bi * NB + lane] = x;
                 }
-                if (t == 0) s_perm[j] = p;
-                __syncthreads();
+                if (lane == 0) L.perm[j] = bi;
+                // the exchanged rows are read by other lanes of this wave
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
                 // multipliers of column j and the rank-1 update of the panel's later columns
                 const double piv = s_panel[j * NB + j];
-                for (int r = j + 1 + t; r < mr; r += kSolveThreads) {
+                for (int r = j + 1 + lane; r < mr; r += kWave) {
                     const double l = s_panel[r * NB + j] / piv;
                     s_panel[r * NB + j] = l;
 #pragma unroll
                     for (int cc = 0; cc < NB; ++cc)
                         if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
                 }
-                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane == 0) L.sing = sing ? 1 : 0;
+        }
+        __syncthreads();
+        return L.sing != 0;
+    }
+    // tall panel: every wave scans rows; four work-group barriers per column
+    for (int j = 0; j < nb; ++j) {
+        double best = -1.0;
+        int bi = mr;
+        for (int r = j + t; r < mr; r += kSolveThreads) {
+            const double v = fabs(s_panel[r * NB + j]);
+            if (v > best) {
+                best = v;
+                bi = r;
             }
         }
-        if (singular) break;
-        // U11 back to A; right of the panel: the row exchanges, then U12 = L11^-1 A12
-        for (int e = t; e < nb * nb; e += kSolveThreads) {
-            const int r = e / nb, j = e - r * nb;
-            A[(k0 + r) * ld + k0 + j] = s_panel[r * NB + j];
+        wave_argmax(best, bi);
+        if (lane == 0) {
+            L.cv[wave] = best;
+            L.ci[wave] = bi;
         }
-        const int c0 = k0 + nb;
-        for (int c = c0 + t; c < (int)ld; c += kSolveThreads) {
-            for (int j = 0; j < nb; ++j) {
-                const int p = s_perm[j];
-                if (p != j) {
-                    const double x = A[(k0 + j) * ld + c];
-                    A[(k0 + j) * ld + c] = A[(k0 + p) * ld + c];
-                    A[(k0 + p) * ld + c] = x;
-                }
-            }
-            double u[NB];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                if (j < nb) {
-                    double v = A[(k0 + j) * ld + c];
-#pragma unroll
-                    for (int i = 0; i < NB; ++i)
-                        if (i < j) v = __builtin_fma(-s_panel[j * NB + i], u[i], v);
-                    u[j] = v;
-                    A[(k0 + j) * ld + c] = v;
-                }
+        __syncthreads();
+        if (wave == 0) {
+            double v = lane < kSolveWaves ? L.cv[lane] : -1.0;
+            int idx = lane < kSolveWaves ? L.ci[lane] : mr;
+            wave_argmax(v, idx);
+            if (lane == 0) {
+                L.pv = v;
+                L.pi = idx;
             }
         }
         __syncthreads();
-        // trailing update A22 -= L21 U12: lanes over 64 consecutive columns; the
-        // waves take (column chunk, row group) tasks
-        const int nchunk = ((int)ld - c0 + kWave - 1) / kWave;
-        const int groups = max(1, kSolveWaves / nchunk);
-        for (int task = wave; task < nchunk * groups; task += kSolveWaves) {
-            const int chunk = task % nchunk, grp = task / nchunk;
-            const int c = c0 + chunk * kWave + lane;
-            const bool live = c < (int)ld;
-            double u[NB];
+        if (!(L.pv > 0.0)) return true;      // zero (or NaN) pivot column: the system is singular
+        const int p = min(max(L.pi, j), mr - 1);    // a candidate row of this column
+        if (t < NB && p != j) {
+            const double x = s_panel[j * NB + t];
+            s_panel[j * NB + t] = s_panel[p * NB + t];
+            s_panel[p * NB + t] = x;
+        }
+        if (t == 0) L.perm[j] = p;
+        __syncthreads();
+        // multipliers of column j and the rank-1 update of the panel's later columns
+        const double piv = s_panel[j * NB + j];
+        for (int r = j + 1 + t; r < mr; r += kSolveThreads) {
+            const double l = s_panel[r * NB + j] / piv;
+            s_panel[r * NB + j] = l;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) u[j] = (live && j < nb) ? A[(k0 + j) * ld + c] : 0.0;
-            for (int i0 = c0 + grp * kRowBatch; i0 < m; i0 += groups * kRowBatch) {
-                double v[kRowBatch];
-#pragma unroll
-                for (int q = 0; q < kRowBatch; ++q) v[q] = (live && i0 + q < m) ? A[(i0 + q) * ld + c] : 0.0;
-#pragma unroll
-                for (int q = 0; q < kRowBatch; ++q) {
-                    if (i0 + q < m) {
-                        const double* L = s_panel + (i0 + q - k0) * NB;
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) v[q] = __builtin_fma(-L[j], u[j], v[q]);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kRowBatch; ++q)
-                    if (live && i0 + q < m) A[(i0 + q) * ld + c] = v[q];
-            }
+            for (int cc = 0; cc < NB; ++cc)
+                if (cc > j && cc < nb) s_panel[r * NB + cc] = __builtin_fma(-l, s_panel[j * NB + cc], s_panel[r * NB + cc]);
         }
         __syncthreads();
     }
+    return false;
+}
 
-    if (singular) {
-        for (long long e = t; e < (long long)nr * m; e += kSolveThreads) a.x[e] = __builtin_nan("");
-        return;
+// Column c right of the panel at k0 (nb columns, factorised in s_panel):
+// the panel's row exchanges, then U12 = L11^-1 A12 in place.
+template <int NB>
+__device__ inline void exchange_and_solve_column(double* A, long long ld, int k0, int nb, const PanelLds<NB>& L,
+                                                 long long c, bool solve) {
+    for (int j = 0; j < nb; ++j) {
+        const int p = L.perm[j];
+        if (p != j) {
+            const double x = A[(k0 + j) * ld + c];
+            A[(k0 + j) * ld + c] = A[(k0 + p) * ld + c];
+            A[(k0 + p) * ld + c] = x;
+        }
     }
-    // back substitution in blocks of kBackBlock rows from the bottom; a chunk
-    // of rc right-hand sides is held in LDS (the panel buffer, free now)
-    double* Ub = s_panel;                                    // [kBackBlock][kBackBlock + 1]
-    double* Xs = s_panel + kBackBlock * (kBackBlock + 1);    // [m][rc]
-    const int rc_max = (kPanelDoubles - kBackBlock * (kBackBlock + 1)) / m;
+    if (!solve) return;
+    double u[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+            double v = A[(k0 + j) * ld + c];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < j) v = __builtin_fma(-L.panel[j * NB + i], u[i], v);
+            u[j] = v;
+            A[(k0 + j) * ld + c] = v;
+        }
+    }
+}
+
+// As exchange_and_solve_column with the exchanges composed (compose_exchanges):
+// every touched row is loaded before any is stored, so the loads overlap.
+template <int NB>
+__device__ inline void permute_and_solve_column(double* A, long long ld, int k0, int nb, const PanelLds<NB>& L,
+                                                long long c, bool solve) {
+    const int n = L.tn;
+    double v[2 * NB];
+#pragma unroll
+    for (int i = 0; i < 2 * NB; ++i)
+        if (i < n) v[i] = A[(k0 + L.tsrc[i]) * ld + c];
+    if (solve) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j < nb) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (i < j) v[j] = __builtin_fma(-L.panel[j * NB + i], v[i], v[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * NB; ++i)
+        if (i < n && (i < nb || L.trow[i] != L.tsrc[i])) A[(k0 + L.trow[i]) * ld + c] = v[i];
+}
+
+// A[r][c] -= L21[r] U12[c] for rows k0+nb .. m-1 and columns c0 .. ce-1
+// (c0 = k0 + nb), L21 in s_panel.  Lanes go over lpr consecutive columns,
+// lpr the narrowest power of two (8 .. 64) that covers them, so a wave works
+// on 64 / lpr row sets at once; the waves take (column chunk, row group)
+// tasks, and each lane loads RB rows before it stores any.
+template <int NB, int RB>
+__device__ inline void panel_trailing_update(double* A, long long ld, int m, int k0, int nb, int ce,
+                                             const PanelLds<NB>& L) {
+    const int t = threadIdx.x;
+    const int lane = t % kWave, wave = t / kWave;
+    const int c0 = k0 + nb, w = ce - c0;
+    int lpr = kWave;
+    while (lpr > 8 && lpr / 2 >= w) lpr /= 2;
+    const int sets = kWave / lpr, sub = lane / lpr, cl = lane % lpr;
+    const int nchunk = (w + lpr - 1) / lpr;
+    const int groups = max(1, kSolveWaves / nchunk);
+    for (int task = wave; task < nchunk * groups; task += kSolveWaves) {
+        const int chunk = task % nchunk, grp = task / nchunk;
+        const int c = c0 + chunk * lpr + cl;
+        const bool live = c < ce;
+        double u[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) u[j] = (live && j < nb) ? A[(k0 + j) * ld + c] : 0.0;
+        for (int i0 = c0 + (grp * sets + sub) * RB; i0 < m; i0 += groups * sets * RB) {
+            double v[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) v[q] = (live && i0 + q < m) ? A[(i0 + q) * ld + c] : 0.0;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (i0 + q < m) {
+                    const double* Lr = L.panel + (i0 + q - k0) * NB;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) v[q] = __builtin_fma(-Lr[j], u[j], v[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (live && i0 + q < m) A[(i0 + q) * ld + c] = v[q];
+        }
+    }
+}
+
+// Back substitution with U in A[0 .. m)[0 .. m) and the right-hand sides in
+// columns m .. m+nr; buf: LDS of buf_doubles >= kBackBlock (kBackBlock + 1) + m.
+__device__ void back_substitute(const double* A, long long ld, int m, int nr, double* x, double* buf,
+                                int buf_doubles) {
+    const int t = threadIdx.x;
+    const int lane = t % kWave, wave = t / kWave;
+    double* Ub = buf;                                    // [kBackBlock][kBackBlock + 1]
+    double* Xs = buf + kBackBlock * (kBackBlock + 1);    // [m][rc]
+    const int rc_max = (buf_doubles - kBackBlock * (kBackBlock + 1)) / m;
     for (int r0 = 0; r0 < nr; r0 += rc_max) {
         const int rc = min(rc_max, nr - r0);
         __syncthreads();
@@ -361,9 +449,291 @@ __global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a
         }
         for (long long e = t; e < (long long)rc * m; e += kSolveThreads) {
             const int c = (int)(e / m), i = (int)(e - (long long)c * m);
-            a.x[(long long)(r0 + c) * m + i] = Xs[i * rc + c];
+            x[(long long)(r0 + c) * m + i] = Xs[i * rc + c];
         }
     }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kSolveThreads) master_solve_kernel(SolveArgs a) {
+    __shared__ PanelLds<NB> L;
+    const int t = threadIdx.x;
+    const int lane = t % kWave, wave = t / kWave;
+    const int m = a.m, nr = a.n_rhs;
+    const long long ld = (long long)m + nr;
+    double* A = a.work;
+
+    // assemble [K | C~]
+    for (int r = wave; r < m; r += kSolveWaves)
+        for (int c = lane; c < (int)ld; c += kWave) A[r * ld + c] = assembled(a, r, c);
+    __syncthreads();
+
+    bool singular = false;
+    for (int k0 = 0; k0 < m; k0 += NB) {
+        const int nb = min(NB, m - k0);
+        const int mr = m - k0;
+        // panel: rows k0 .. m-1, columns k0 .. k0+nb-1
+        load_panel<NB>(L, A, ld, k0, mr, nb);
+        __syncthreads();
+        singular = factor_panel<NB>(L, mr, nb);
+        if (singular) break;
+        // U11 back to A; right of the panel: the row exchanges, then U12 = L11^-1 A12
+        for (int e = t; e < nb * nb; e += kSolveThreads) {
+            const int r = e / nb, j = e - r * nb;
+            A[(k0 + r) * ld + k0 + j] = L.panel[r * NB + j];
+        }
+        for (int c = k0 + nb + t; c < (int)ld; c += kSolveThreads) exchange_and_solve_column<NB>(A, ld, k0, nb, L, c, true);
+        __syncthreads();
+        panel_trailing_update<NB, kRowBatch>(A, ld, m, k0, nb, (int)ld, L);
+        __syncthreads();
+    }
+
+    if (singular) {
+        for (long long e = t; e < (long long)nr * m; e += kSolveThreads) a.x[e] = __builtin_nan("");
+        return;
+    }
+    // back substitution; the panel buffer is free now
+    back_substitute(A, ld, m, nr, a.x, L.panel, kPanelDoubles);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-work-group path (m >= kMultiMin).
+constexpr int kOuterNB = 32;               // columns per outer panel
+constexpr int kSingularSlot = kOuterNB;    // x[kSingularSlot]: an outer panel met a zero pivot
+constexpr int kSwapCols = 64;              // columns per work-group of the swap + TRSM kernel
+constexpr int kSwapThreads = 256;
+constexpr int kUpdTile = 64;               // the update kernel's tile: kUpdTile x kUpdTile entries
+constexpr int kUpdThreads = 256;           // 16 x 16 threads, 4 x 4 entries each
+constexpr int kBackDoubles = 20000;        // back-substitution LDS (m <= 15840 with one right-hand side)
+static_assert(kOuterNB <= kWave, "the swap kernel's mapping keeps two touched rows per lane of one wave");
+constexpr int kPanelRowBatch = 16;         // rows loaded before any is stored in the panel kernel's update
+constexpr int kMultiMin = 400;             // systems of at least this many unknowns take this path
+static_assert(kMultiMin > kSingularSlot, "x must hold the pivots and the flag");
+static_assert((kSolveMaxCols - 1) * 4 <= kPanelDoubles, "every panel's rows must fit an LDS panel of 4 columns");
+
+struct OuterArgs {
+    double* A;                   // the augmented matrix [m][ld]
+    double* x;                   // pivots of the outer panel in x[0 .. nbo), the flag in x[kSingularSlot]
+    long long ld;
+    int m, k0, nbo;
+};
+
+__global__ void __launch_bounds__(256) solve_assemble_kernel(SolveArgs a) {
+    const int r = blockIdx.x;
+    const long long ld = (long long)a.m + a.n_rhs;
+    for (int c = threadIdx.x; c < (int)ld; c += 256) a.work[r * ld + c] = assembled(a, r, c);
+}
+
+// One work-group factorises the outer panel: columns k0 .. k0+nbo-1, rows
+// k0 .. m-1, in inner panels of NB columns.  Every inner panel is written back
+// whole (its multipliers are the L21 of the update kernel), its row exchanges
+// go to the outer panel's other columns (left ones too, so L21 stays in row
+// order) and its U12 and trailing update stay inside the outer panel.
+template <int NB>
+__global__ void __launch_bounds__(kSolveThreads) solve_panel_kernel(OuterArgs a) {
+    __shared__ PanelLds<NB> L;
+    const int t = threadIdx.x;
+    const int m = a.m, k0 = a.k0, ce = a.k0 + a.nbo;
+    const long long ld = a.ld;
+    double* A = a.A;
+    if (k0 == 0) {
+        if (t == 0) a.x[kSingularSlot] = 0.0;
+    } else if (a.x[kSingularSlot] != 0.0) {
+        return;                                   // an earlier panel was singular
+    }
+    for (int kk = k0; kk < ce; kk += NB) {
+        const int nb = min(NB, ce - kk), mr = m - kk;
+        load_panel<NB>(L, A, ld, kk, mr, nb);
+        __syncthreads();
+        if (factor_panel<NB>(L, mr, nb)) {
+            if (t == 0) a.x[kSingularSlot] = 1.0;
+            return;
+        }
+        for (int e = t; e < mr * nb; e += kSolveThreads) {
+            const int r = e / nb, j = e - r * nb;
+            A[(kk + r) * ld + kk + j] = L.panel[r * NB + j];
+        }
+        if (t < nb) a.x[kk - k0 + t] = (double)(kk + L.perm[t]);
+        if (t == 0) compose_exchanges<NB>(L, nb);
+        __syncthreads();
+        // the other columns of the outer panel: left ones get the exchanges,
+        // right ones the exchanges and U12
+        const int nleft = kk - k0, nother = nleft + (ce - kk - nb);
+        for (int q = t; q < nother; q += kSolveThreads) {
+            const int c = q < nleft ? k0 + q : kk + nb + (q - nleft);
+            permute_and_solve_column<NB>(A, ld, kk, nb, L, c, q >= nleft);
+        }
+        __syncthreads();
+        if (kk + nb < ce) panel_trailing_update<NB, kPanelRowBatch>(A, ld, m, kk, nb, ce, L);
+        __syncthreads();
+    }
+}
+
+// Right of the outer panel, kSwapCols columns per work-group: the nbo row
+// exchanges of the panel composed into one permutation of the rows they touch
+// (the top block k0 .. k0+nbo-1 and at most nbo rows below it), applied by
+// reading every source row before writing any, then U12 = L11^-1 A12 for the
+// top block (one thread per column).
+__global__ void __launch_bounds__(kSwapThreads) solve_swap_trsm_kernel(OuterArgs a) {
+    __shared__ double s_l[kOuterNB][kOuterNB + 1];
+    __shared__ double s_tile[2 * kOuterNB][kSwapCols];
+    __shared__ int s_row[2 * kWave];             // touched rows: the top block first (two per lane)
+    __shared__ int s_src[2 * kWave];             // the row whose old values land in s_row[i]
+    __shared__ int s_n;
+    if (a.x[kSingularSlot] != 0.0) return;
+    const int t = threadIdx.x;
+    const int lane = t % kSwapCols, grp = t / kSwapCols;
+    constexpr int kGroups = kSwapThreads / kSwapCols;
+    const int k0 = a.k0, nbo = a.nbo;
+    const long long ld = a.ld;
+    const double* Ac = a.A;
+    const long long c = (long long)(k0 + nbo) + (long long)blockIdx.x * kSwapCols + lane;
+    const bool live = c < ld;
+    // L11: every thread issues its 16 loads before it stores any
+    {
+        constexpr int kPer = kOuterNB * kOuterNB / kSwapThreads;
+        double v[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = t + q * kSwapThreads, r = e / kOuterNB, j = e - r * kOuterNB;
+            v[q] = (r < nbo && j < nbo) ? Ac[(k0 + r) * ld + k0 + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = t + q * kSwapThreads, r = e / kOuterNB, j = e - r * kOuterNB;
+            s_l[r][j] = v[q];
+        }
+    }
+    if (t < kWave) {
+        // one wave: lane i keeps touched rows i and i + 64 in registers; a
+        // ballot finds where the pivot row sits
+        const int l = t;
+        int row0 = l < nbo ? k0 + l : -1, src0 = row0;
+        int row1 = -1, src1 = -1;
+        int n = nbo;
+        const int piv = l < nbo ? (int)a.x[l] : 0;       // all pivots in one load
+        for (int j = 0; j < nbo; ++j) {
+            const int p = __shfl(piv, j);
+            if (p == k0 + j) continue;
+            const unsigned long long h0 = __ballot(row0 == p), h1 = __ballot(row1 == p);
+            int ip;
+            if (h0) {
+                ip = __ffsll((long long)h0) - 1;
+            } else if (h1) {
+                ip = kWave + __ffsll((long long)h1) - 1;
+            } else {
+                ip = n++;
+                if (l == ip - kWave) row1 = src1 = p;     // p > k0 + nbo - 1 here, so ip >= nbo
+                if (ip < kWave && l == ip) row0 = src0 = p;
+            }
+            // swap the sources of positions j (< nbo <= 64) and ip
+            const int sj = __shfl(src0, j);
+            const int sip = ip < kWave ? __shfl(src0, ip) : __shfl(src1, ip - kWave);
+            if (l == j) src0 = sip;
+            if (ip < kWave) {
+                if (l == ip) src0 = sj;
+            } else if (l == ip - kWave) {
+                src1 = sj;
+            }
+        }
+        s_row[l] = row0;
+        s_src[l] = src0;
+        s_row[kWave + l] = row1;
+        s_src[kWave + l] = src1;
+        if (l == 0) s_n = n;
+    }
+    __syncthreads();
+    const int n = s_n;
+    {
+        constexpr int kPer = 2 * kOuterNB / kGroups;     // touched rows per thread, loaded before any store
+        double v[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = grp + q * kGroups;
+            v[q] = (i < n && live) ? Ac[(long long)s_src[i] * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = grp + q * kGroups;
+            if (i < n) s_tile[i][lane] = v[q];
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+    double* A = a.A;
+    for (int i = nbo + grp; i < n; i += kGroups) A[(long long)s_row[i] * ld + c] = s_tile[i][lane];
+    if (grp == 0) {
+        for (int j = 0; j < nbo; ++j) {
+            double v = s_tile[j][lane];
+            for (int i = 0; i < j; ++i) v = __builtin_fma(-s_l[j][i], s_tile[i][lane], v);
+            s_tile[j][lane] = v;
+            A[(k0 + j) * ld + c] = v;
+        }
+    }
+}
+
+// A22 -= L21 U12 over rows and columns k0+nbo .. (m and ld), depth nbo:
+// kUpdTile x kUpdTile entries per work-group, 4 x 4 per thread.
+__global__ void __launch_bounds__(kUpdThreads) solve_update_kernel(OuterArgs a) {
+    __shared__ double s_lt[kOuterNB][kUpdTile + 1];    // L21 transposed: [k][row]
+    __shared__ double s_u[kOuterNB][kUpdTile];         // U12: [k][column]
+    if (a.x[kSingularSlot] != 0.0) return;
+    const int t = threadIdx.x;
+    const int tr = t / 16, tc = t % 16;
+    const int k0 = a.k0, nbo = a.nbo, m = a.m;
+    const long long ld = a.ld;
+    const long long c0 = (long long)k0 + nbo;
+    const long long rb = c0 + (long long)blockIdx.y * kUpdTile, cb = c0 + (long long)blockIdx.x * kUpdTile;
+    double* A = a.A;
+    for (int e = t; e < kUpdTile * kOuterNB; e += kUpdThreads) {
+        const int r = e / kOuterNB, k = e - r * kOuterNB;
+        s_lt[k][r] = (k < nbo && rb + r < m) ? A[(rb + r) * ld + k0 + k] : 0.0;
+    }
+    for (int e = t; e < kOuterNB * kUpdTile; e += kUpdThreads) {
+        const int k = e / kUpdTile, cc = e - k * kUpdTile;
+        s_u[k][cc] = (k < nbo && cb + cc < ld) ? A[(k0 + k) * ld + cb + cc] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k = 0; k < nbo; ++k) {
+        double l[4], u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            l[q] = s_lt[k][tr * 4 + q];
+            u[q] = s_u[k][tc * 4 + q];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(l[i], u[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long r = rb + tr * 4 + i;
+        if (r >= m) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long c = cb + tc * 4 + j;
+            if (c < ld) A[r * ld + c] -= acc[i][j];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSolveThreads) solve_back_kernel(SolveArgs a) {
+    __shared__ double buf[kBackDoubles];
+    const int t = threadIdx.x;
+    const int m = a.m, nr = a.n_rhs;
+    const bool singular = a.x[kSingularSlot] != 0.0;
+    __syncthreads();                              // every thread has read the flag before x is written
+    if (singular) {
+        for (long long e = t; e < (long long)nr * m; e += kSolveThreads) a.x[e] = __builtin_nan("");
+        return;
+    }
+    back_substitute(a.work, (long long)m + nr, m, nr, a.x, buf, kBackDoubles);
 }
 
 }  // namespace
@@ -422,11 +792,39 @@ hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const
     a.n_rhs = n_rhs;
     a.pol = pol;
     if (a.m + n_rhs > kSolveMaxCols) return hipErrorInvalidValue;
-    // the widest panel whose m rows fit in LDS (16 columns would spill registers)
-    if (a.m * 8 <= kPanelDoubles)
-        hipLaunchKernelGGL(master_solve_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(master_solve_kernel<4>, dim3(1), dim3(kSolveThreads), 0, s, a);
+    if (a.m < kMultiMin) {
+        // the widest panel whose m rows fit in LDS (16 columns would spill registers)
+        if (a.m * 8 <= kPanelDoubles)
+            hipLaunchKernelGGL(master_solve_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(master_solve_kernel<4>, dim3(1), dim3(kSolveThreads), 0, s, a);
+        return hipGetLastError();
+    }
+    const int m = a.m;
+    const long long ld = (long long)m + n_rhs;
+    hipLaunchKernelGGL(solve_assemble_kernel, dim3((unsigned)m), dim3(256), 0, s, a);
+    for (int k0 = 0; k0 < m; k0 += kOuterNB) {
+        OuterArgs o;
+        o.A = work;
+        o.x = x;
+        o.ld = ld;
+        o.m = m;
+        o.k0 = k0;
+        o.nbo = min(kOuterNB, m - k0);
+        if ((m - k0) * 8 <= kPanelDoubles)
+            hipLaunchKernelGGL(solve_panel_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, o);
+        else
+            hipLaunchKernelGGL(solve_panel_kernel<4>, dim3(1), dim3(kSolveThreads), 0, s, o);
+        const long long c0 = (long long)k0 + o.nbo;    // < ld: there is at least one right-hand side
+        const unsigned col_groups = (unsigned)((ld - c0 + kSwapCols - 1) / kSwapCols);
+        hipLaunchKernelGGL(solve_swap_trsm_kernel, dim3(col_groups), dim3(kSwapThreads), 0, s, o);
+        if (c0 < m)
+            hipLaunchKernelGGL(solve_update_kernel,
+                               dim3((unsigned)((ld - c0 + kUpdTile - 1) / kUpdTile),
+                                    (unsigned)((m - c0 + kUpdTile - 1) / kUpdTile)),
+                               dim3(kUpdThreads), 0, s, o);
+    }
+    hipLaunchKernelGGL(solve_back_kernel, dim3(1), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
 

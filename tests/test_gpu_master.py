@@ -5,8 +5,9 @@ against the oracle (oracle/master.py, numpy's LAPACK solve).
 * Random TT and E/B block systems, one and several right-hand sides, a system
   that needs row exchanges: agreement with numpy within a bound from the
   condition number.
-* A singular system gives NaN (small, and 700 unknowns through the tall
-  panels); argument errors are caught on the host.
+* A singular system gives NaN (small, 100 unknowns on one work-group, 700
+  through the multi-work-group path and its tall panels); argument errors are
+  caught on the host.
 * End to end: windows -> binned K (couple_band) -> pseudo-spectra of a C_l
   that is constant inside each bin -> solve.  For such a C_l the binned
   relation of Sec. 2 eq. pseudo_cl is exact, so the solve must return the
@@ -79,7 +80,8 @@ def test_bin_spectra(torch_gpu, ctx, n_bins, width):
     assert np.array_equal(one, got[1])
 
 
-@pytest.mark.parametrize("n,n_rhs", [(1, 1), (2, 1), (63, 1), (64, 3), (65, 1), (200, 2), (1023, 1), (4000, 96)])
+@pytest.mark.parametrize("n,n_rhs", [(1, 1), (2, 1), (63, 1), (64, 3), (65, 1), (200, 2), (399, 1), (400, 1), (401, 2),
+                                     (1023, 1), (2049, 3), (4000, 96)])
 def test_solve_tt_random(torch_gpu, ctx, n, n_rhs):
     from paper_2602_15605_amd import couple
     torch = torch_gpu
@@ -110,12 +112,13 @@ def test_solve_pol_random(torch_gpu, ctx, n, n_rhs):
     assert np.max(np.abs(x[:, n:] - bb)) <= bound
 
 
-def test_solve_needs_row_exchanges(torch_gpu, ctx):
+@pytest.mark.parametrize("n", [50, 450])
+def test_solve_needs_row_exchanges(torch_gpu, ctx, n):
     """A permutation matrix has zeros on the diagonal: elimination without row
-    exchanges would divide by zero; with them the solution is exact."""
+    exchanges would divide by zero; with them the solution is exact (one
+    work-group at 50 unknowns, the multi-work-group path at 450)."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
-    n = 50
     perm = np.random.default_rng(5).permutation(n)
     while np.any(perm == np.arange(n)):
         perm = np.random.default_rng(int(perm[0]) + 7).permutation(n)
@@ -143,22 +146,36 @@ def test_singular_system_gives_nan(torch_gpu, ctx):
 
 
 def test_singular_tall_system_gives_nan(torch_gpu, ctx):
-    """Two equal rows in a 700-unknown system (panels taller than one wave
-    handles, then short ones): both rows get the same updates, so when one
-    becomes a pivot the other is reduced to exact zeros and a later pivot
-    column is zero."""
+    """Singular systems of 100 and 700 unknowns give NaN.
+
+    * 100 unknowns (one work-group): two equal rows.  Both get the same
+      updates, so when one becomes a pivot the other is reduced to exact zeros
+      and a later pivot column is zero.
+    * 700 unknowns (outer panels spread over the chip): a zero column.  Every
+      update subtracts multiples of that column's U entries, which are zero,
+      so it stays exactly zero under any blocking; placed at 3 it is met in a
+      panel taller than one wave handles, at 650 in a short one.  (Equal rows
+      are not used here: the blocked update sums a row's multipliers in
+      another order than the pivot row's own elimination, so the difference
+      is rounding-sized, not zero.)
+    """
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     rng = np.random.default_rng(700)
-    A = _system(700, rng)
-    A[650] = A[10]
-    x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, rng.standard_normal((2, 700)))).cpu().numpy()
-    assert x.shape == (2, 700) and np.all(np.isnan(x))
-    # the same system with the row restored solves
-    A[650] = _system(700, np.random.default_rng(700))[650]
+    A = _system(100, rng)
+    A[90] = A[10]
+    x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, rng.standard_normal((2, 100)))).cpu().numpy()
+    assert x.shape == (2, 100) and np.all(np.isnan(x))
+    for col in (3, 650):
+        A = _system(700, rng)
+        A[:, col] = 0.0
+        x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, rng.standard_normal((2, 700)))).cpu().numpy()
+        assert x.shape == (2, 700) and np.all(np.isnan(x)), col
+    # a system of the same size right after solves (the flag is cleared)
+    A = _system(700, np.random.default_rng(701))
     b = rng.standard_normal(700)
     x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, b)).cpu().numpy()
-    _check_solution(x, A, b, "restored 700")
+    _check_solution(x, A, b, "700 after singular")
 
 
 def test_argument_errors(torch_gpu, ctx):
