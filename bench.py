@@ -36,6 +36,9 @@ FLOP_PER_TRIPLE_POL = 12
 # The method's count with X^2 formed per triple (three multiplies), as the paper's
 # evaluation of eq. 000_sq_main does: TT 5 + TE/EE 11.  Reported as the effective rate.
 FLOP_PER_TRIPLE_PAPER = 16
+# The band-limited call asks for TT, EE and BB only, so the strip runs without the TE
+# accumulation: 12 - 2.
+FLOP_PER_TRIPLE_BAND = 10
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "strip_pol4_lmax6000_traffic.md")
@@ -61,6 +64,16 @@ def measured_traffic(kernel: str):
         if line.startswith("kernel_source_sha256"):
             digest = line.split("=")[1].strip()
     return value if digest == h.hexdigest() else None
+
+
+def band_triples(lmax: int, cut: int) -> int:
+    """Even-L triples with l1 <= l2 <= lmax and l3 <= cut (the band-limited sum)."""
+    total = 0
+    for d in range(0, min(cut, lmax) + 1):
+        l1 = np.arange(0, lmax - d + 1, dtype=np.int64)
+        top = np.minimum(2 * l1 + d, cut)
+        total += int(np.sum((top - d) // 2 + 1))
+    return total
 
 
 def triples(lmax: int) -> int:
@@ -266,12 +279,27 @@ def run_extras(torch, couple, synth, args):
     dW = [[torch.as_tensor(masks[m][s]).cuda() for m in range(8)] for s in range(3)]
     edges = list(range(0, 10001, 50))
     res = torch.empty((8, 3, 200, 200), dtype=torch.float64, device="cuda")
+    T_band = band_triples(L, cut)
     for prec in ("fp32c", "fp64"):
-        ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,
-                                                              spectra=("TT", "EE", "BB"), precision=prec,
-                                                              bin_edges=edges, out=res), steps, warm)
+        call = lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L, spectra=("TT", "EE", "BB"),
+                                                  precision=prec, bin_edges=edges, out=res)
+        ms = _timed(torch, call, steps, warm)
+        couple.couple_profile(ctx, True)
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        prof = couple.couple_profile_read(ctx)
+        couple.couple_profile(ctx, False)
+        kms = {k: prof[k][0] / steps for k in ("scale_windows", "strip", "fill")}
+        # TT and EE per triple (no TE): P, the TT FMA, the t step, the N' FMA, two multiplies, the EE FMA
+        tflops = FLOP_PER_TRIPLE_BAND * T_band * 8 / (kms["strip"] * 1e-3) / 1e12
+        peak = PEAK_VALU_TFLOPS[prec]
         out["band_lmax10000_cut1000_8masks_binned_" + prec] = {
-            "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200}
+            "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200,
+            "kernel_ms_per_call": kms, "launches_per_call": {k: prof[k][1] / steps for k in kms},
+            "triples_per_mask": T_band, "flop_per_triple": FLOP_PER_TRIPLE_BAND,
+            "strip_tflops": tflops, "strip_roofline_frac": tflops / peak,
+            "note": "eight launch chains (windows, strip, bin) of one mask each"}
     # the same band-limited call writing the symmetric kernels Xi (the covariance kernels when
     # the windows are squared-mask spectra)
     ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,
