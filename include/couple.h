@@ -324,7 +324,7 @@ int couple_threej_rows_m(couple_ctx *ctx, int m1, int m2, int n_pairs, const int
  *   rhs  : device float64 [n_rhs][m] (binned pseudo-spectra, EE then BB).
  *   work : device float64 workspace of m * (m + n_rhs) entries, overwritten.
  *   x    : device float64 [n_rhs][m], the solution.
- *   m + n_rhs <= 4096.  Gaussian elimination with partial pivoting in
+ *   m + n_rhs <= 15840.  Gaussian elimination with partial pivoting in
  *   float64; K and rhs are not modified.  Below 400 unknowns one work-group
  *   runs it all (one kernel).  From 400 on, outer panels of 32 columns are
  *   factorised by one work-group each while the row exchanges, U12 and the

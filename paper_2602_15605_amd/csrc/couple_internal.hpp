@@ -115,7 +115,7 @@ hipError_t launch_threej_family(const couple_ctx* ctx, int rot, int flip, int a,
                                 const int* l2, double* out, long long stride, hipStream_t s);
 
 // binned MASTER solve (solve.hip)
-constexpr int kSolveMaxCols = 4096;    // unknowns + right-hand sides of one solve
+constexpr int kSolveMaxCols = 15840;   // unknowns + right-hand sides of one solve
 hipError_t launch_bin_spectra(const couple_ctx* ctx, int n_spec, const double* cl, int cl_stride,
                               const int* bin_edges_host, int n_bins, double* out, hipStream_t s);
 hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const double* rhs, double* work,

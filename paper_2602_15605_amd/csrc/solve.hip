@@ -14,8 +14,8 @@
 // the first row on ties) on the augmented matrix [K | C~] (TT, or the 2 x 2
 // block system for E/B) in the caller's workspace, then back substitution.
 // Panels are factorised in LDS by one work-group:
-//   * a panel of NB columns (8, or 4 when its rows would not fit) by one wave,
-//     with no work-group barrier per column, when it has at most
+//   * a panel of NB columns (8, or 4, 2 or 1 when its rows would not fit) by
+//     one wave, with no work-group barrier per column, when it has at most
 //     kWavePanelRows rows, else by every wave; the pivot's arg-max over a wave
 //     runs on DPP lane moves;
 //   * right of the panel, each column applies the panel's row exchanges and
@@ -507,9 +507,12 @@ constexpr int kUpdThreads = 256;           // 16 x 16 threads, 4 x 4 entries eac
 constexpr int kBackDoubles = 20000;        // back-substitution LDS (m <= 15840 with one right-hand side)
 static_assert(kOuterNB <= kWave, "the swap kernel's mapping keeps two touched rows per lane of one wave");
 constexpr int kPanelRowBatch = 16;         // rows loaded before any is stored in the panel kernel's update
+                                           // (half that for 8-column panels, which would spill)
 constexpr int kMultiMin = 400;             // systems of at least this many unknowns take this path
 static_assert(kMultiMin > kSingularSlot, "x must hold the pivots and the flag");
-static_assert((kSolveMaxCols - 1) * 4 <= kPanelDoubles, "every panel's rows must fit an LDS panel of 4 columns");
+static_assert(kSolveMaxCols - 1 <= kPanelDoubles, "every panel's rows must fit an LDS panel of one column");
+static_assert(kBackBlock * (kBackBlock + 1) + kSolveMaxCols <= kBackDoubles,
+              "back substitution holds at least one right-hand side of every system in LDS");
 
 struct OuterArgs {
     double* A;                   // the augmented matrix [m][ld]
@@ -564,7 +567,7 @@ __global__ void __launch_bounds__(kSolveThreads) solve_panel_kernel(OuterArgs a)
             permute_and_solve_column<NB>(A, ld, kk, nb, L, c, q >= nleft);
         }
         __syncthreads();
-        if (kk + nb < ce) panel_trailing_update<NB, kPanelRowBatch>(A, ld, m, kk, nb, ce, L);
+        if (kk + nb < ce) panel_trailing_update<NB, (NB >= 8 ? kPanelRowBatch / 2 : kPanelRowBatch)>(A, ld, m, kk, nb, ce, L);
         __syncthreads();
     }
 }
@@ -793,7 +796,7 @@ hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const
     a.pol = pol;
     if (a.m + n_rhs > kSolveMaxCols) return hipErrorInvalidValue;
     if (a.m < kMultiMin) {
-        // the widest panel whose m rows fit in LDS (16 columns would spill registers)
+        // the widest panel whose m rows fit in LDS (16 columns would spill registers; m < 400 here)
         if (a.m * 8 <= kPanelDoubles)
             hipLaunchKernelGGL(master_solve_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, a);
         else
@@ -811,10 +814,15 @@ hipError_t launch_master_solve(int pol, int n, const double* K, int n_rhs, const
         o.m = m;
         o.k0 = k0;
         o.nbo = min(kOuterNB, m - k0);
+        // the widest inner panel whose rows fit in LDS
         if ((m - k0) * 8 <= kPanelDoubles)
             hipLaunchKernelGGL(solve_panel_kernel<8>, dim3(1), dim3(kSolveThreads), 0, s, o);
-        else
+        else if ((m - k0) * 4 <= kPanelDoubles)
             hipLaunchKernelGGL(solve_panel_kernel<4>, dim3(1), dim3(kSolveThreads), 0, s, o);
+        else if ((m - k0) * 2 <= kPanelDoubles)
+            hipLaunchKernelGGL(solve_panel_kernel<2>, dim3(1), dim3(kSolveThreads), 0, s, o);
+        else
+            hipLaunchKernelGGL(solve_panel_kernel<1>, dim3(1), dim3(kSolveThreads), 0, s, o);
         const long long c0 = (long long)k0 + o.nbo;    // < ld: there is at least one right-hand side
         const unsigned col_groups = (unsigned)((ld - c0 + kSwapCols - 1) / kSwapCols);
         hipLaunchKernelGGL(solve_swap_trsm_kernel, dim3(col_groups), dim3(kSwapThreads), 0, s, o);

@@ -4,7 +4,7 @@ against the oracle (oracle/master.py, numpy's LAPACK solve).
 * Binning of pseudo-spectra, ragged bins, more than 512 bins (staged edges).
 * Random TT and E/B block systems, one and several right-hand sides, a system
   that needs row exchanges: agreement with numpy within a bound from the
-  condition number.
+  condition number; systems of 6000 to 9000 unknowns by their backward error.
 * A singular system gives NaN (small, 100 unknowns on one work-group, 700
   through the multi-work-group path and its tall panels); argument errors are
   caught on the host.
@@ -92,6 +92,36 @@ def test_solve_tt_random(torch_gpu, ctx, n, n_rhs):
     x = couple.couple_master_solve(ctx, _gpu(torch, A), _gpu(torch, b)).cpu().numpy()
     err = _check_solution(x, A, b, "TT n=%d" % n)
     _say("  max abs err %.2e" % err)
+
+
+@pytest.mark.parametrize("n,pol", [(6000, False), (9000, False), (3100, True)])
+def test_solve_large(torch_gpu, ctx, n, pol):
+    """Systems beyond 4096 unknowns, whose first panels are factorised 2 (over
+    4096 rows) and 1 (over 8192 rows) columns at a time: the backward error
+    |A x - b| / (|A| |x|) within 64 m eps (a condition number costs too much
+    here), and the solution against LAPACK where that is affordable."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    m = 2 * n if pol else n
+    _say("solve large m=%d" % m)
+    rng = np.random.default_rng(m)
+    if pol:
+        K3 = np.stack([_system(n, rng), _system(n, rng), 0.05 * rng.standard_normal((n, n))])
+        A = np.block([[K3[0], K3[2]], [K3[2], K3[1]]])
+        Kg = _gpu(torch, K3)
+    else:
+        A = _system(n, rng)
+        Kg = _gpu(torch, A)
+    b = rng.standard_normal(m)
+    x = couple.couple_master_solve(ctx, Kg, _gpu(torch, b), pol=pol).cpu().numpy()
+    assert np.all(np.isfinite(x))
+    r = np.abs(A @ x - b).max()
+    berr = r / (np.abs(A).sum(axis=1).max() * np.abs(x).max())
+    _say("  backward error %.2e" % berr)
+    assert berr <= 64 * m * np.finfo(float).eps
+    if m <= 6200:
+        ref = np.linalg.solve(A, b)
+        assert np.abs(x - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("n,n_rhs", [(1, 1), (31, 2), (200, 1), (1000, 4)])
@@ -189,8 +219,9 @@ def test_argument_errors(torch_gpu, ctx):
     assert lib.couple_master_solve(h, 2, 4, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
     assert lib.couple_master_solve(h, 0, 0, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
     assert lib.couple_master_solve(h, 0, 4, p, 0, p, p, p, None) == couple.COUPLE_EINVAL
-    assert lib.couple_master_solve(h, 0, 4096, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
-    assert lib.couple_master_solve(h, 1, 2048, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
+    assert lib.couple_master_solve(h, 0, 15840, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
+    assert lib.couple_master_solve(h, 1, 7920, p, 1, p, p, p, None) == couple.COUPLE_EINVAL
+    assert lib.couple_master_solve(h, 0, 15000, p, 841, p, p, p, None) == couple.COUPLE_EINVAL
     assert "exceed" in couple.couple_last_error(ctx)
     assert lib.couple_master_solve(h, 0, 4, None, 1, p, p, p, None) == couple.COUPLE_EINVAL
     odd = ctypes.c_void_p(t.data_ptr() + 4)
