@@ -127,8 +127,10 @@ __device__ inline void decode_item(const BatchArgs& a, int item, int* grp_out, i
 
 // Stage the chunk of k = kch .. kch + KC - 1: the g / h windows of the
 // wavefront's rows, S(k) = g(k) g(d+k) (0 outside 0 <= k <= kmax) and
-// D(k) = c(d + 2k) - c(d + 2 kch), an integer exact in float32.  Fully
-// unrolled, so every global load is in flight before the first LDS write.
+// D(k) = c(d + 2k) - c(d + 2 ke), ke = max(kch, 0) the chunk's expansion
+// point (chunk_expansion), an integer exact in float32 while below 2^24 (l3 up
+// to about 8000) and rounded once above.  Fully unrolled, so every global load
+// is in flight before the first LDS write.
 template <int TM, int KC>
 __device__ inline void stage_chunk(const BatchArgs& a, float* s_g, float* s_h, float* s_s, float* s_dc, int A0,
                                    int d, int kch, int kmax, int lane) {
@@ -161,7 +163,7 @@ __device__ inline void stage_chunk(const BatchArgs& a, float* s_g, float* s_h, f
             s_h[slot] = hv[i];
         }
     }
-    const int l3c = d + 2 * kch;
+    const int l3c = d + 2 * max(kch, 0);
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
         const int s = lane + kBThreads * i;
@@ -199,16 +201,33 @@ __device__ inline void store_xi(const BatchArgs& a, int grp, int d, int A0, int 
         }
 }
 
-// Row constants: gam = a + b - 1 (exact int) and beta = 2ab + 1 (float32),
-// with N' = t^2 - beta and t = c - gam.
+// Row constants: gam = a + b - 1 and beta = 2ab + 1, both exact, with
+// N' = t^2 - beta and t = c - gam.
 template <int TM>
-__device__ inline void row_constants(int A0, int d, int r, int (&gam)[TM], float (&beta)[TM]) {
+__device__ inline void row_constants(int A0, int d, int r, int (&gam)[TM], long long (&beta)[TM]) {
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
         const long long l1 = A0 + 16 * t + r, l2 = l1 + d;
         const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
         gam[t] = (int)(aa + bb - 1);
-        beta[t] = (float)(2.0 * (double)aa * (double)bb + 1.0);
+        beta[t] = 2 * aa * bb + 1;
+    }
+}
+
+// N' expanded about a chunk's first valid l3 (c_s = l3c (l3c + 1), l3c for
+// k = max(kch, 0): a point outside the row's range would inflate Q): with
+// T = c_s - gam and D = c - c_s, N' = Q + D (2T + D), Q = T^2 - beta exact in
+// int64.  Per step N' = fma(D, rf + D, qf) with qf = fl(Q), rf = fl(2T): the
+// cancellation of t^2 against beta happens exactly, once per chunk.
+template <int TM>
+__device__ inline void chunk_expansion(int l3c, const int (&gam)[TM], const long long (&beta)[TM], float (&qf)[TM],
+                                       float (&rf)[TM]) {
+    const long long c = (long long)l3c * (l3c + 1);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+        const long long T = c - gam[t];
+        qf[t] = (float)(double)(T * T - beta[t]);
+        rf[t] = 2.0f * (float)T;
     }
 }
 
@@ -260,7 +279,7 @@ batched_mfma_f32_kernel(BatchArgs a) {
     constexpr int kStepRows = 8 * kGroup;
 
     int gam[TM];
-    float beta[TM];
+    long long beta[TM];
     row_constants<TM>(A0, d, r, gam, beta);
     f4v acc[TM][3];
     float ks[TM][3][4], kc[TM][3][4];
@@ -289,14 +308,8 @@ batched_mfma_f32_kernel(BatchArgs a) {
         const int kc_n = min(KC, kmax - kch + 1);
         __syncthreads();
         stage_chunk<TM, KC>(a, s_g, s_h, s_s, s_dc, A0, d, kch, kmax, lane);
-        const int l3c = d + 2 * kch;
-        float thi[TM], tlo[TM];
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-            const int T = l3c * (l3c + 1) - gam[t];
-            thi[t] = (float)T;
-            tlo[t] = (float)(T - (int)thi[t]);
-        }
+        float qf[TM], rf[TM];
+        chunk_expansion<TM>(d + 2 * max(kch, 0), gam, beta, qf, rf);
         __syncthreads();
         const int g_base = A0 - kch - KC - 3;
 
@@ -311,8 +324,7 @@ batched_mfma_f32_kernel(BatchArgs a) {
                 const float gv = s_g[l1 - (kch + s) - g_base];
                 const float hv = s_h[l1 - A0 + s];
                 x2[t] = S * (gv * hv);
-                const float tt = thi[t] + (D + tlo[t]);
-                const float N = __builtin_fmaf(tt, tt, -beta[t]);
+                const float N = __builtin_fmaf(D, rf[t] + D, qf[t]);
                 y[t] = x2[t] * N;
                 z[t] = y[t] * N;
             }
@@ -757,7 +769,7 @@ batched_mfma_bf16x3_kernel(BatchArgs a) {
     };
 
     int gam[TM];
-    float beta[TM];
+    long long beta[TM];
     row_constants<TM>(A0, d, r, gam, beta);
     f4v acc[TM][3];
     float ks[TM][3][4], kc[TM][3][4];
@@ -779,14 +791,8 @@ batched_mfma_bf16x3_kernel(BatchArgs a) {
     for (int kch = k_org; kch <= kmax; kch += KC) {
         __syncthreads();
         stage_chunk<TM, KC>(a, s_g, s_h, s_s, s_dc, A0, d, kch, kmax, lane);
-        const int l3c = d + 2 * kch;
-        float thi[TM], tlo[TM];
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-            const int T = l3c * (l3c + 1) - gam[t];
-            thi[t] = (float)T;
-            tlo[t] = (float)(T - (int)thi[t]);
-        }
+        float qf[TM], rf[TM];
+        chunk_expansion<TM>(d + 2 * max(kch, 0), gam, beta, qf, rf);
         __syncthreads();
         const int g_base = A0 - kch - KC - 3;
 
@@ -817,8 +823,7 @@ batched_mfma_bf16x3_kernel(BatchArgs a) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     v[e] = S[e] * (pg[-e] * ph[e]);
-                    const float tt = thi[t] + (D[e] + tlo[t]);
-                    N[e] = __builtin_fmaf(tt, tt, -beta[t]);
+                    N[e] = __builtin_fmaf(D[e], rf[t] + D[e], qf[t]);
                 }
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
