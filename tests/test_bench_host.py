@@ -19,3 +19,21 @@ def test_te_plain_error():
     K = np.array([1.0 + 1e-9, -2.0 - 4e-9, 1.0, 0.0])
     # the third element is below the 1e-3 floor and the fourth has A_ref = 0
     assert abs(bench.te_plain_error(K, K_ref, A_ref) - 2e-9) < 1e-15
+
+
+def test_band_triples_brute_force():
+    """The band-limited triple count the band roofline divides by: even-L
+    (l1 <= l2 <= lmax, l3 <= cut) triples, against a direct count."""
+    import bench
+
+    def brute(L, cut):
+        n = 0
+        for l1 in range(L + 1):
+            for l2 in range(l1, L + 1):
+                for l3 in range(l2 - l1, min(l1 + l2, cut) + 1):
+                    n += (l1 + l2 + l3) % 2 == 0
+        return n
+
+    for L, cut in ((10, 4), (20, 7), (15, 40), (30, 0), (25, 25)):
+        assert bench.band_triples(L, cut) == brute(L, cut), (L, cut)
+    assert bench.band_triples(12, 10 ** 6) == bench.triples(12)
