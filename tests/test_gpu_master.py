@@ -13,7 +13,7 @@ against the oracle (oracle/master.py, numpy's LAPACK solve).
   relation of Sec. 2 eq. pseudo_cl is exact, so the solve must return the
   bin values of C_l; the oracle's own chain (oracle K, binned, LAPACK)
   agrees with it.
-* One captured graph of bin + solve replays to the eager result.
+* One captured graph of bin + solve replays to the eager result, on both paths.
 """
 import math
 import sys
@@ -284,11 +284,12 @@ def test_master_end_to_end(torch_gpu, ctx, oracle_bulk, precision):
         precision, np.max(np.abs(x[:nb] - c_ee) / c_ee), np.max(np.abs(x[nb:] - c_bb) / c_bb)))
 
 
-def test_graph_replay(torch_gpu, ctx):
+@pytest.mark.parametrize("n", [120, 600])
+def test_graph_replay(torch_gpu, ctx, n):
+    """One launch below 400 unknowns, the multi-work-group sequence above."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     rng = np.random.default_rng(3)
-    n = 120
     K = _gpu(torch, _system(n, rng))
     cl = _gpu(torch, rng.uniform(0.5, 1.5, 3 * n))
     edges = list(range(0, 3 * n + 1, 3))
