@@ -284,22 +284,26 @@ def test_master_end_to_end(torch_gpu, ctx, oracle_bulk, precision):
         precision, np.max(np.abs(x[:nb] - c_ee) / c_ee), np.max(np.abs(x[nb:] - c_bb) / c_bb)))
 
 
-@pytest.mark.parametrize("n", [120, 600])
-def test_graph_replay(torch_gpu, ctx, n):
-    """One launch below 400 unknowns, the multi-work-group sequence above."""
+@pytest.mark.parametrize("n,pol", [(120, False), (300, True)])
+def test_graph_replay(torch_gpu, ctx, n, pol):
+    """One launch for 120 unknowns (TT); the multi-work-group sequence for the
+    600-unknown E/B block.  Up to 512 bins the binning is capturable too."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     rng = np.random.default_rng(3)
-    K = _gpu(torch, _system(n, rng))
-    cl = _gpu(torch, rng.uniform(0.5, 1.5, 3 * n))
+    m = 2 * n if pol else n
+    K = _gpu(torch, np.stack([_system(n, rng), _system(n, rng), 0.05 * rng.standard_normal((n, n))])
+             if pol else _system(n, rng))
+    ns = 2 if pol else 1
+    cl = _gpu(torch, rng.uniform(0.5, 1.5, (ns, 3 * n)))
     edges = list(range(0, 3 * n + 1, 3))
-    work = torch.empty(n * (n + 1), dtype=torch.float64, device="cuda")
-    ctb = torch.empty((1, n), dtype=torch.float64, device="cuda")
-    x = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    work = torch.empty(m * (m + 1), dtype=torch.float64, device="cuda")
+    ctb = torch.empty((ns, n), dtype=torch.float64, device="cuda")
+    x = torch.empty((1, m), dtype=torch.float64, device="cuda")
 
     def call():
-        couple.couple_bin_spectra(ctx, cl.reshape(1, -1), edges, out=ctb)
-        couple.couple_master_solve(ctx, K, ctb, work=work, out=x)
+        couple.couple_bin_spectra(ctx, cl, edges, out=ctb)
+        couple.couple_master_solve(ctx, K, ctb.reshape(1, -1), pol=pol, work=work, out=x)
 
     call()
     torch.cuda.synchronize()
