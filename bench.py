@@ -271,7 +271,7 @@ def run_extras(torch, couple, synth, args):
     """The band-limited and batched workloads, timed the same way (device time
     per call, inputs resident); reported beside the headline, not as it."""
     out = {}
-    steps, warm = 3, 1
+    steps, warm = 8, 3
     # band-limited: lmax=10000, l3<=1000, 8 masks, TT/EE/BB, 200 bins of 50, FP32C
     L, cut = 10000, 1000
     ctx = couple.couple_init(L)
