@@ -656,40 +656,12 @@ static long long count_items(int lmax, int dmax, int B, bool band) {
     return (long long)B * (M + 1) * (M + 2) / 2;
 }
 
-hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo, int l3_hi,
-                        hipStream_t s) {
-    constexpr int R = kStripR;
-    StripArgs a;
-    a.g = ctx->g_pad + kTablePad;
-    a.h = ctx->h_pad + kTablePad;
-    a.wp = ctx->wp;
-    a.cl = ctx->cl;
-    a.xi = ctx->xi;
-    a.xi_stride = tri_size(lmax);
-    a.wp_stride = 2 * ctx->lmax_max + 1;
-    a.g_len = ctx->lmax_max + 1;
-    a.h_len = 2 * ctx->lmax_max + 1;
-    a.lmax = lmax;
-    a.dmax = std::min(lmax, l3_hi);
-    a.l3_lo = l3_lo;
-    a.l3_hi = l3_hi;
-    a.band = a.dmax < lmax ? 1 : 0;
-    if (mode == kStripTT) {
-        constexpr int RT = kStripRTT;
-        const long long n_tt = count_items(lmax, a.dmax, kWave * RT, a.band != 0);
-        if (n_tt <= 0) return hipSuccess;
-        if (n_tt > 0x7fffffffLL) return hipErrorInvalidValue;
-        const dim3 grid((unsigned)n_tt), block(kWave);
-        if (precision == COUPLE_FP32C)
-            hipLaunchKernelGGL((strip_fp32c_kernel<RT, kModeTT>), grid, block, 0, s, a, ctx->gf_pad + kTablePad,
-                               ctx->hf_pad + kTablePad);
-        else
-            hipLaunchKernelGGL((strip_fp64_kernel<RT, kModeTT, false>), grid, block, 0, s, a);
-        return hipGetLastError();
-    }
-    const long long n_items = count_items(lmax, a.dmax, kWave * R, a.band != 0);
-    if (n_items <= 0) return hipSuccess;
-    if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
+namespace {
+
+// The polarised and EB modes for one row count R per lane.
+template <int R>
+hipError_t launch_strip_modes(const couple_ctx* ctx, const StripArgs& a, int lmax, int mode, int precision,
+                              long long n_items, hipStream_t s) {
     const dim3 grid((unsigned)n_items), block(kWave);
     if (precision == COUPLE_FP32C) {
         const float* gf = ctx->gf_pad + kTablePad;
@@ -725,4 +697,51 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     return hipGetLastError();
 }
 
+}  // namespace
+
+hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo, int l3_hi,
+                        hipStream_t s) {
+    constexpr int R = kStripR;
+    StripArgs a;
+    a.g = ctx->g_pad + kTablePad;
+    a.h = ctx->h_pad + kTablePad;
+    a.wp = ctx->wp;
+    a.cl = ctx->cl;
+    a.xi = ctx->xi;
+    a.xi_stride = tri_size(lmax);
+    a.wp_stride = 2 * ctx->lmax_max + 1;
+    a.g_len = ctx->lmax_max + 1;
+    a.h_len = 2 * ctx->lmax_max + 1;
+    a.lmax = lmax;
+    a.dmax = std::min(lmax, l3_hi);
+    a.l3_lo = l3_lo;
+    a.l3_hi = l3_hi;
+    a.band = a.dmax < lmax ? 1 : 0;
+    if (mode == kStripTT) {
+        constexpr int RT = kStripRTT;
+        const long long n_tt = count_items(lmax, a.dmax, kWave * RT, a.band != 0);
+        if (n_tt <= 0) return hipSuccess;
+        if (n_tt > 0x7fffffffLL) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)n_tt), block(kWave);
+        if (precision == COUPLE_FP32C)
+            hipLaunchKernelGGL((strip_fp32c_kernel<RT, kModeTT>), grid, block, 0, s, a, ctx->gf_pad + kTablePad,
+                               ctx->hf_pad + kTablePad);
+        else
+            hipLaunchKernelGGL((strip_fp64_kernel<RT, kModeTT, false>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
+    // 256-row blocks (R = 4) unless they would leave the chip short of work
+    // items: then 128-row blocks (R = 2)
+    const long long n4 = count_items(lmax, a.dmax, kWave * R, a.band != 0);
+    if (n4 <= 0) return hipSuccess;
+    if (n4 < (precision == COUPLE_FP32C ? kStripSmallItemsF32 : kStripSmallItemsF64)) {
+        const long long n2 = count_items(lmax, a.dmax, kWave * kStripRSmall, a.band != 0);
+        if (n2 > 0x7fffffffLL) return hipErrorInvalidValue;
+        return launch_strip_modes<kStripRSmall>(ctx, a, lmax, mode, precision, n2, s);
+    }
+    if (n4 > 0x7fffffffLL) return hipErrorInvalidValue;
+    return launch_strip_modes<R>(ctx, a, lmax, mode, precision, n4, s);
+}
+
 }  // namespace couple
+

@@ -16,6 +16,14 @@ constexpr int kStripR = 4;
 // The TT-only sum costs two operations per term, so there the two window
 // reads per step dominate; eight rows per lane halve them per term.
 constexpr int kStripRTT = 8;
+// Launches that would have fewer work items of 64 R rows than these take
+// kStripRSmall rows per lane, four times as many items with a quarter of the
+// staircase each: float32 below 8192 items (full triangle: lmax <= 1918),
+// float64 below 4096 (lmax <= 1321), where the measured crossovers lie; above them the
+// longer rows per lane win.
+constexpr int kStripRSmall = 2;
+constexpr long long kStripSmallItemsF32 = 8192;
+constexpr long long kStripSmallItemsF64 = 4096;
 
 // l3 steps staged in LDS per chunk by the float64 and float32 strip kernels.
 constexpr int kStripChunkF64 = 256;

@@ -211,6 +211,25 @@ def test_full_matrix_lmax2000(torch_gpu, ctx, oracle_bulk, precision, tol, workl
         _say("  %s max rel err %.3e" % (s, err))
 
 
+@pytest.mark.parametrize("precision,tol,lmax", [("fp32c", TOL_FP32C, 1918), ("fp32c", TOL_FP32C, 1919),
+                                                  ("fp64", TOL_FP64, 1321), ("fp64", TOL_FP64, 1322),
+                                                  ("fp64", TOL_FP64, 1000), ("fp32c", TOL_FP32C, 1000)])
+def test_row_block_switch(torch_gpu, ctx, oracle_bulk, precision, tol, lmax):
+    """Both sides of the size below which the strip kernels take 128-row
+    blocks (two rows per lane) instead of 256: 1918 / 1919 in FP32C, 1321 /
+    1322 in FP64, on sampled rows and both ends, all four spectra and EB.
+    The FP32C cases use the l_c = 1500 windows of the FP32C workload."""
+    from paper_2602_15605_amd import synth
+    spec5 = SPEC4 + ("EB",)
+    Ws = synth.workload_windows(1 if precision == "fp64" else 2, lmax=lmax)
+    K = _run(torch_gpu, ctx, Ws, lmax, spectra=spec5, precision=precision)
+    rows = np.unique(np.concatenate([synth.sample_rows(lmax, fraction=0.02), [lmax - 1, lmax // 3]])).astype(np.int32)
+    _say("row block switch %s lmax %d: %d rows" % (precision, lmax, len(rows)))
+    Kr, Ar = _oracle(oracle_bulk, Ws, lmax, spectra=spec5, rows=rows)
+    for i, s in enumerate(spec5):
+        assert_parity(K[i][rows], Kr[i], Ar[i], tol, "%s lmax %d %s" % (precision, lmax, s))
+
+
 def test_workload2_fp64_sampled_rows(torch_gpu, ctx, oracle_bulk):
     from paper_2602_15605_amd import synth
     lmax = 6000
