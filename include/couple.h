@@ -70,9 +70,13 @@ enum couple_spectrum {
 enum couple_precision {
     COUPLE_FP64 = 0,   /* float64 throughout                                          */
     COUPLE_FP32C = 1,  /* float32 terms with compensated accumulation; float64 tables,
-                          window scaling and final rescale                             */
+                          window scaling and final rescale.  Each block of terms is
+                          scaled by a power of two from the largest |W'| it can meet,
+                          so windows far outside float32's range are handled       */
     COUPLE_MFMA_FP32 = 2, /* batched form only: float32 matrix-core contraction of the
-                             3j^2 tiles against the windows, Kahan-flushed accumulators */
+                             3j^2 tiles against the windows, Kahan-flushed accumulators;
+                             W' = (2l+1) W_l / 4 pi is rounded to float32 unscaled, so
+                             terms whose W' lies below its normal range are lost     */
     COUPLE_MFMA_BF16X3 = 3 /* batched form only: the same contraction on bfloat16
                               matrix cores with both operands split hi + lo and three
                               products (hi*hi + hi*lo + lo*hi) accumulated in float32;

@@ -98,6 +98,7 @@ void release(couple_ctx* c) {
     (void)hipFree(c->xi);
     (void)hipFree(c->wp);
     (void)hipFree(c->wpf);
+    (void)hipFree(c->wexp);
     (void)hipFree(c->edges_dev);
     if (c->edges_host) (void)hipHostFree(c->edges_host);
     delete c;
@@ -152,6 +153,11 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
                                          (spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB)) ? W_PP : nullptr, n, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
+    if (precision == COUPLE_FP32C) {
+        Timed t(ctx, s, 0);
+        e = couple::launch_window_exponents(ctx, n, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
     if (even) {
         Timed t(ctx, s, 1);
         const int mode = !pol                    ? couple::kStripTT
@@ -219,6 +225,7 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
         {(void**)&c->cl, (lmax_max + 1) * sizeof(double)},
         {(void**)&c->xi, 4 * (size_t)couple::tri_size(lmax_max) * sizeof(double)},
         {(void**)&c->wp, nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
+        {(void**)&c->wexp, nw * sizeof(int)},
         {(void**)&c->edges_dev, (lmax_max + 2) * sizeof(int)},
     };
     size_t total = 0;

@@ -42,6 +42,7 @@ struct couple_ctx {
     double* xi = nullptr;        // 4 packed upper triangles (TT, TE, EE, EB)
     double* wp = nullptr;        // scaled windows (2l+1) W_l / (4 pi), 3 x (2 lmax_max + 1)
     float* wpf = nullptr;        // float32 copies
+    int* wexp = nullptr;         // FP32C scale exponents: suffix maxima of |W'| per parity, 3 x (2 lmax_max + 1)
     int* edges_dev = nullptr;    // bin edges (device), lmax_max + 2
     int* edges_host = nullptr;   // pinned staging for the bin edges
     double* solve_scratch = nullptr;  // this device's copy of the no-alloc solve workspace
@@ -75,6 +76,9 @@ hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
 //   kStripEB: Xi_EB (odd L, fourth triangle).  l3 restricted to [l3_lo, l3_hi].
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
                                 const double* wpp, int n, hipStream_t s);
+// wexp[x][l3] = e with max |W'_x(l3')| over l3' = l3, l3 + 2, .. < n in [2^(e-1), 2^e)
+// (0 where that maximum is 0), for the float32 strip kernels' per-item scaling
+hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s);
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,
                         int l3_hi, hipStream_t s);
 

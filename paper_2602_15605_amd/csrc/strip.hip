@@ -89,10 +89,49 @@ __global__ void scale_windows_kernel(const double* __restrict__ wtt, const doubl
     wpf[2 * stride + l] = (float)c;
 }
 
+// Exponent of the suffix maximum of |W'_x| over each parity: one work-group per
+// (spectrum x, parity p), threads over contiguous runs of l3 = p + 2 i.  Each
+// run's maximum, a suffix maximum across the runs (Hillis-Steele in LDS), then
+// each run walked backwards.  The float32 strip kernels scale an item's
+// staged U by 2^-e at its first l3 (the largest |W'| it can meet then lies in
+// [1/2, 1)) and its sums back by 2^e in float64, both exact: a window whose
+// tail falls below float32's normal range (about 1e-38) then still leaves
+// the terms that dominate every element inside it.
+constexpr int kExpThreads = 1024;
+__global__ void __launch_bounds__(kExpThreads) window_exponents_kernel(const double* __restrict__ wp, int n,
+                                                                      int stride, int* __restrict__ wexp) {
+    __shared__ double s_max[kExpThreads];
+    const int x = blockIdx.x >> 1, p = blockIdx.x & 1;
+    const int cnt = n > p ? (n - p + 1) / 2 : 0;
+    const int per = (cnt + kExpThreads - 1) / kExpThreads;
+    const int t = threadIdx.x;
+    const int i0 = min(cnt, t * per), i1 = min(cnt, i0 + per);
+    const double* w = wp + (long long)x * stride + p;
+    int* e = wexp + (long long)x * stride + p;
+    double m = 0.0;
+    for (int i = i0; i < i1; ++i) m = fmax(m, fabs(w[2 * i]));
+    s_max[t] = m;
+    __syncthreads();
+    for (int off = 1; off < kExpThreads; off <<= 1) {
+        const double v = t + off < kExpThreads ? s_max[t + off] : 0.0;
+        __syncthreads();
+        s_max[t] = fmax(s_max[t], v);
+        __syncthreads();
+    }
+    double run = t + 1 < kExpThreads ? s_max[t + 1] : 0.0;
+    for (int i = i1 - 1; i >= i0; --i) {
+        run = fmax(run, fabs(w[2 * i]));
+        int ex = 0;
+        if (run > 0.0) (void)frexp(run, &ex);
+        e[2 * i] = min(1000, max(-1000, ex));
+    }
+}
+
 struct StripArgs {
     const double* g;     // g(p), index 0 = p 0, valid 0 .. lmax_max
     const double* h;     // 1/((2p+1) g(p)), valid 0 .. 2 lmax_max
     const double* wp;    // scaled windows, 3 x wp_stride
+    const int* wexp;     // float32 kernels: exponents of the suffix maxima of |W'| (window_exponents_kernel)
     const double* cl;    // c_l
     double* xi;          // 3 packed triangles of xi_stride
     long long xi_stride;
@@ -462,6 +501,10 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     const double* wtt = a.wp;
     const double* wtp = a.wp + a.wp_stride;
     const double* wpp = a.wp + 2 * a.wp_stride;
+    // per-item power-of-two scales of U (exact): from the largest |W'| at or above
+    // the item's first l3, so the dominant terms sit near 1 in float32
+    const int l3f = min(de + 2 * k_lo, a.l3_hi);      // an item with no step in the band stores zeros
+    const int ex_tt = a.wexp[l3f], ex_tp = a.wexp[a.wp_stride + l3f], ex_pp = a.wexp[2 * a.wp_stride + l3f];
 
     for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
         const int kc = min(KC, k_hi - k0 + 1);
@@ -487,13 +530,13 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
                 const double gg = a.g[k] * a.g[de + k];
                 if (EB) {
                     const long long c = (long long)l3 * (l3 + 1);
-                    u.x = (float)(wpp[l3] * gg * (double)(c - (long long)d * (d + 1)));
+                    u.x = (float)(ldexp(wpp[l3] * gg, -ex_pp) * (double)(c - (long long)d * (d + 1)));
                     u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
                 } else {
-                    if (TTS) u.x = (float)(wtt[l3] * gg);
+                    if (TTS) u.x = (float)ldexp(wtt[l3] * gg, -ex_tt);
                     if (POL) {
-                        if (TE) u.y = (float)(wtp[l3] * gg);
-                        u.z = (float)(wpp[l3] * gg);
+                        if (TE) u.y = (float)ldexp(wtp[l3] * gg, -ex_tp);
+                        u.z = (float)ldexp(wpp[l3] * gg, -ex_pp);
                         u.w = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
                     }
                 }
@@ -623,14 +666,14 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
         if (l1 >= 0 && l1 < n_valid) {
             if (EB) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
-                a.xi[3 * a.xi_stride + off + l1] = (s * s) * ((double)kt[j] - (double)ct[j]);
+                a.xi[3 * a.xi_stride + off + l1] = ldexp((s * s) * ((double)kt[j] - (double)ct[j]), ex_pp);
                 continue;
             }
-            if (TTS) a.xi[off + l1] = (double)kt[j] - (double)ct[j];
+            if (TTS) a.xi[off + l1] = ldexp((double)kt[j] - (double)ct[j], ex_tt);
             if (POL) {
                 const double s = 0.5 * a.cl[l1] * a.cl[l1 + d];
-                if (TE) a.xi[a.xi_stride + off + l1] = s * ((double)kte[j] - (double)cte[j]);
-                a.xi[2 * a.xi_stride + off + l1] = (s * s) * ((double)kee[j] - (double)cee[j]);
+                if (TE) a.xi[a.xi_stride + off + l1] = ldexp(s * ((double)kte[j] - (double)cte[j]), ex_tp);
+                a.xi[2 * a.xi_stride + off + l1] = ldexp((s * s) * ((double)kee[j] - (double)cee[j]), ex_pp);
             }
         }
     }
@@ -643,6 +686,12 @@ hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const 
     const int stride = 2 * ctx->lmax_max + 1;
     hipLaunchKernelGGL(scale_windows_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wtt, wtp, wpp, n,
                        stride, ctx->wp, ctx->wpf);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s) {
+    hipLaunchKernelGGL(window_exponents_kernel, dim3(6), dim3(kExpThreads), 0, s, ctx->wp, n, 2 * ctx->lmax_max + 1,
+                       ctx->wexp);
     return hipGetLastError();
 }
 
@@ -706,6 +755,7 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     a.g = ctx->g_pad + kTablePad;
     a.h = ctx->h_pad + kTablePad;
     a.wp = ctx->wp;
+    a.wexp = ctx->wexp;
     a.cl = ctx->cl;
     a.xi = ctx->xi;
     a.xi_stride = tri_size(lmax);

@@ -192,11 +192,15 @@ def test_workload1_sampled_rows(torch_gpu, ctx, oracle_bulk):
         assert np.max(np.abs(xi - xi.T) / scale) < 1e-15
 
 
-@pytest.mark.parametrize("precision,tol,workload", [("fp64", TOL_FP64, 1), ("fp32c", TOL_FP32C, 2)])
+@pytest.mark.parametrize("precision,tol,workload", [("fp64", TOL_FP64, 1), ("fp32c", TOL_FP32C, 2),
+                                                     ("fp32c", TOL_FP32C, 1)])
 def test_full_matrix_lmax2000(torch_gpu, ctx, oracle_bulk, precision, tol, workload):
     """Every element of the four 2001 x 2001 matrices against the oracle: the
-    pol4_lmax2000 windows in FP64; the l_c = 1500 windows of the FP32C
-    workload (whose K stays in the float32 range) in FP32C."""
+    pol4_lmax2000 windows (l_c = 300, 250, 200) in FP64 and FP32C, and the
+    l_c = 1500 windows of the FP32C workload in FP32C.  With l_c = 200 the PP
+    window falls below float32's normal range (about 1e-38) from about l3 = 1790 on,
+    so the far diagonals of K^EE hold only such terms: FP32C keeps them
+    through its per-item power-of-two scales."""
     import os
     import time
     from paper_2602_15605_amd import synth
@@ -228,6 +232,27 @@ def test_row_block_switch(torch_gpu, ctx, oracle_bulk, precision, tol, lmax):
     Kr, Ar = _oracle(oracle_bulk, Ws, lmax, spectra=spec5, rows=rows)
     for i, s in enumerate(spec5):
         assert_parity(K[i][rows], Kr[i], Ar[i], tol, "%s lmax %d %s" % (precision, lmax, s))
+
+
+@pytest.mark.parametrize("lmax", [1918, 2100])
+def test_fp32c_window_tails_below_float32(torch_gpu, ctx, oracle_bulk, lmax):
+    """FP32C with windows whose tails leave float32's range: the pol4_lmax2000
+    windows taken to lmax 1918 (128-row blocks) and 2100 (256-row blocks),
+    where W'_PP(l3) is below 1e-38 from about l3 = 1790 on and below 1e-60 at the
+    far corner.  Sampled rows (rows 0 .. 2 reach the last diagonals), all four
+    spectra and EB; the far corner of every spectrum is non-zero."""
+    from paper_2602_15605_amd import synth
+    spec5 = SPEC4 + ("EB",)
+    Ws = synth.workload_windows(1, lmax=lmax)
+    assert Ws[2][2 * lmax] < 1e-60
+    K = _run(torch_gpu, ctx, Ws, lmax, spectra=spec5, precision="fp32c")
+    rows = np.unique(np.concatenate([synth.sample_rows(lmax, fraction=0.02), [lmax - 1, lmax // 3]])).astype(np.int32)
+    _say("fp32c window tails lmax %d: %d rows" % (lmax, len(rows)))
+    Kr, Ar = _oracle(oracle_bulk, Ws, lmax, spectra=spec5, rows=rows)
+    for i, s in enumerate(spec5):
+        err = assert_parity(K[i][rows], Kr[i], Ar[i], TOL_FP32C, "fp32c tails lmax %d %s" % (lmax, s))
+        _say("  %s max rel err %.3e" % (s, err))
+        assert np.all(K[i][2:5, lmax - 2:] != 0.0), s
 
 
 def test_workload2_fp64_sampled_rows(torch_gpu, ctx, oracle_bulk):
