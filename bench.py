@@ -299,7 +299,8 @@ def run_extras(torch, couple, synth, args):
             "kernel_ms_per_call": kms, "launches_per_call": {k: prof[k][1] / steps for k in kms},
             "triples_per_mask": T_band, "flop_per_triple": FLOP_PER_TRIPLE_BAND,
             "strip_tflops": tflops, "strip_roofline_frac": tflops / peak,
-            "note": "eight launch chains (windows, strip, bin) of one mask each"}
+            "note": ("fp32c: two multi-mask strip launches of four masks (windows once per group), "
+                     "then one bin launch per mask; fp64: eight per-mask launch chains (windows, strip, bin)")}
     # the same band-limited call writing the symmetric kernels Xi (the covariance kernels when
     # the windows are squared-mask spectra)
     ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,

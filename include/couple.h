@@ -166,8 +166,15 @@ int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const
                 const int *bin_edges, int n_bins, double *out, void *stream);
 
 /*
- * couple_band_batched -- couple_band for n_masks windows in one call (the
- * per-mask work is enqueued back to back on `stream`).
+ * couple_band_batched -- couple_band for n_masks windows in one call.  In
+ * COUPLE_FP32C without EB, up to four masks (two when TE is asked for) share
+ * one strip launch: the g/h factors and the (-2 2 0) polynomial of each term
+ * are formed once for them, and each mask's sums are those of couple_band
+ * (the results are bitwise equal).  Such a group needs its Xi triangles of
+ * diagonals 0 .. min(lmax, l3_hi) in the context's workspace, 3 per mask; the
+ * group is cut to what fits, and where a single mask is left the per-mask
+ * launches run.  Other precisions and EB: per-mask work back to back on
+ * `stream`.
  *   W_TT, W_TP, W_PP : HOST arrays of n_masks DEVICE pointers (an array may
  *                      be NULL when no requested spectrum uses it).
  *   out              : device float64, n_masks consecutive outputs of the

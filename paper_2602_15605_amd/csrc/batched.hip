@@ -1104,6 +1104,7 @@ hipError_t launch_batched(couple_ctx* ctx, const BatchPlan& p, int precision, co
             for (int m = 0; m < p.n_masks[gi]; ++m) {
                 FillJob& j = jobs[n_jobs++];
                 j.xi = xi + xi_off[gi][m];
+                j.xi_stride = tri_size(p.lmax[gi][m]);
                 j.out = p.out[gi][m];
                 j.lmax = p.lmax[gi][m];
                 j.dmax = p.lmax[gi][m];

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/couple.h: argument checks,
 // context ownership and the launch sequence
 //   scale windows -> strip (l3 reduction on the upper triangle) -> fill or bin.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -139,6 +140,15 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
     return COUPLE_OK;
 }
 
+// The even-L strip mode a call's spectra need.
+int strip_mode(unsigned spectra) {
+    const bool pol = (spectra & (COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0;
+    return !pol                    ? couple::kStripTT
+           : (spectra & COUPLE_TE) ? couple::kStripPol
+           : (spectra & COUPLE_TT) ? couple::kStripPolEE
+                                   : couple::kStripEE;
+}
+
 int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const double* W_PP, int lmax,
                   unsigned spectra, int precision, int l3_lo, int l3_hi, hipStream_t s) {
     const bool pol = (spectra & (COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0;
@@ -160,12 +170,7 @@ int run_reduction(couple_ctx* ctx, const double* W_TT, const double* W_TP, const
     if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
     if (even) {
         Timed t(ctx, s, 1);
-        const int mode = !pol                    ? couple::kStripTT
-                         : (spectra & COUPLE_TE) ? couple::kStripPol
-                         : (spectra & COUPLE_TT) ? couple::kStripPolEE
-                                                 : couple::kStripEE;
-        e = couple::launch_strip(ctx, lmax, mode, precision, l3_lo,
-                                 std::min(l3_hi, 2 * lmax), s);
+        e = couple::launch_strip(ctx, lmax, strip_mode(spectra), precision, l3_lo, std::min(l3_hi, 2 * lmax), s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "strip launch");
     if (spectra & COUPLE_EB) {
@@ -224,8 +229,8 @@ int couple_init(int lmax_max, couple_ctx** out_ctx) {
         {(void**)&c->gf_pad, ng * sizeof(float)},   {(void**)&c->hf_pad, nh * sizeof(float)},
         {(void**)&c->cl, (lmax_max + 1) * sizeof(double)},
         {(void**)&c->xi, 4 * (size_t)couple::tri_size(lmax_max) * sizeof(double)},
-        {(void**)&c->wp, nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
-        {(void**)&c->wexp, nw * sizeof(int)},
+        {(void**)&c->wp, couple::kBandMasks * nw * sizeof(double)},      {(void**)&c->wpf, nw * sizeof(float)},
+        {(void**)&c->wexp, couple::kBandMasks * nw * sizeof(int)},
         {(void**)&c->edges_dev, (lmax_max + 2) * sizeof(int)},
     };
     size_t total = 0;
@@ -366,6 +371,65 @@ int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const do
     return COUPLE_OK;
 }
 
+// Masks per launch of the multi-mask FP32C strip for a batched band call, or 1
+// where it does not apply: it needs FP32C, even L only (no EB), a non-empty
+// band, and room in the Xi workspace for the group's triangles of diagonals
+// 0 .. dmax (three per mask, TT, TE and EE slots).
+int masks_per_launch(const couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, int lmax, unsigned spectra,
+                     int precision) {
+    if (precision != COUPLE_FP32C || n_masks < 2 || (spectra & COUPLE_EB)) return 1;
+    const int hi = std::min(l3_hi, 2 * lmax);
+    if (l3_lo > hi) return 1;
+    const long long band = couple::diag_offset(lmax, std::min(lmax, hi) + 1);
+    const long long room = 4 * couple::tri_size(ctx->lmax_max) / (3 * band);
+    const int per = couple::strip_masks_per_launch(strip_mode(spectra));
+    return (int)std::min<long long>({(long long)per, room, (long long)n_masks});
+}
+
+// n_masks (<= kBandMasks) masks of a batched band call in one strip launch:
+// their windows are scaled into the context's window sets 0 .. n_masks - 1,
+// the strip writes each mask's Xi triangles (stride: diagonals 0 .. dmax) one
+// after the other, and each mask is filled or binned from its own.
+int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
+               const double* const* W_TP, const double* const* W_PP, int lmax, unsigned spectra,
+               const int* bin_edges, int n_bins, double* out, size_t per_mask, hipStream_t s) {
+    const int hi = std::min(l3_hi, 2 * lmax);
+    const int dmax = std::min(lmax, hi);
+    const int n = hi + 1;
+    const long long stride = couple::diag_offset(lmax, dmax + 1);
+    hipError_t e;
+    {
+        Timed t(ctx, s, 0);
+        e = couple::launch_scale_windows_masks(ctx, (spectra & COUPLE_TT) ? W_TT : nullptr,
+                                               (spectra & COUPLE_TE) ? W_TP : nullptr,
+                                               (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n_masks, n, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
+    {
+        Timed t(ctx, s, 0);
+        e = couple::launch_window_exponents(ctx, n, s, n_masks);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
+    {
+        Timed t(ctx, s, 1);
+        e = couple::launch_strip_masks(ctx, lmax, strip_mode(spectra), n_masks, l3_lo, hi, stride, s);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
+    int src[couple::kMaxOut];
+    const int n_out = output_sources(spectra, src);
+    const int xi = (spectra & COUPLE_XI) ? 1 : 0;
+    for (int m = 0; m < n_masks && e == hipSuccess; ++m) {
+        Timed t(ctx, s, 2);
+        const double* xm = ctx->xi + 3 * stride * m;
+        double* om = out + m * per_mask;
+        e = bin_edges ? couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, om, xi, s,
+                                           xm, stride)
+                      : couple::launch_fill(ctx, lmax, dmax, src, n_out, om, xi, s, xm, stride);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, bin_edges ? "bin launch" : "fill launch");
+    return COUPLE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -416,6 +480,17 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
     int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     const size_t per_mask = bin_edges ? (size_t)n_out * n_bins * n_bins : (size_t)n_out * (lmax + 1) * (lmax + 1);
+    const int group = masks_per_launch(ctx, n_masks, l3_lo, l3_hi, lmax, spectra, precision);
+    if (group > 1) {
+        for (int m0 = 0; m0 < n_masks; m0 += group) {
+            const int g = std::min(group, n_masks - m0);
+            rc = band_masks(ctx, g, l3_lo, l3_hi, need_tt ? W_TT + m0 : nullptr, need_tp ? W_TP + m0 : nullptr,
+                            need_pp ? W_PP + m0 : nullptr, lmax, spectra, bin_edges, n_bins, out + m0 * per_mask,
+                            per_mask, s);
+            if (rc) return rc;
+        }
+        return COUPLE_OK;
+    }
     for (int m = 0; m < n_masks; ++m) {
         rc = band_one(ctx, l3_lo, l3_hi, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
                       need_pp ? W_PP[m] : nullptr, lmax, spectra, precision, bin_edges, n_bins,

@@ -76,30 +76,45 @@ hipError_t launch_build_tables(couple_ctx* ctx, hipStream_t s);
 //   kStripEB: Xi_EB (odd L, fourth triangle).  l3 restricted to [l3_lo, l3_hi].
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
                                 const double* wpp, int n, hipStream_t s);
+// The windows of n_masks <= kBandMasks masks into the context's window sets
+// 0 .. n_masks - 1 (float64 only), for launch_strip_masks; wtt/wtp/wpp NULL
+// where the spectrum is not needed.
+hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const* wtt, const double* const* wtp,
+                                      const double* const* wpp, int n_masks, int n, hipStream_t s);
 // wexp[x][l3] = e with max |W'_x(l3')| over l3' = l3, l3 + 2, .. < n in [2^(e-1), 2^e)
 // (0 where that maximum is 0), for the float32 strip kernels' per-item scaling
-hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s);
+// for window sets 0 .. n_masks - 1
+hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s, int n_masks = 1);
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,
                         int l3_hi, hipStream_t s);
+// Masks one launch_strip_masks call takes in a mode (1: the mode has no such kernel).
+int strip_masks_per_launch(int mode);
+// FP32C over masks 0 .. n_masks - 1 (n_masks <= strip_masks_per_launch) of the window sets,
+// even-L modes: mask m's Xi triangles (TT, TE, EE slots) at xi + 3 m xi_stride.
+hipError_t launch_strip_masks(const couple_ctx* ctx, int lmax, int mode, int n_masks, int l3_lo, int l3_hi,
+                              long long xi_stride, hipStream_t s);
 
 // fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
 //   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE, 3 EB) output i comes from, n_out <= kMaxOut outputs.
 constexpr int kMaxOut = 5;
 //   xi != 0: write Xi itself (no (2 l2 + 1) column factor).
+//   xi_src / xi_stride: the Xi store to read (default: the context's, stride tri(lmax)).
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                       double* out, int xi, hipStream_t s);
+                       double* out, int xi, hipStream_t s, const double* xi_src = nullptr,
+                       long long xi_stride = 0);
 // Up to kInlineBins bins the edges travel in the kernel arguments (no upload,
 // nothing to synchronise); longer lists are read from bin_edges_dev.
 constexpr int kInlineBins = 512;
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                       const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
-                      hipStream_t s);
+                      hipStream_t s, const double* xi_src = nullptr, long long xi_stride = 0);
 // One fill job: Xi store [3][tri(lmax)] (Xi for diagonals d <= dmax, 0 beyond)
 // and its n_out output matrices [n_out][lmax+1][lmax+1].  block0 is set by
 // launch_fill_jobs.
 constexpr int kMaxFillJobs = kMaxGroups * kMaskGroup;
 struct FillJob {
     const double* xi;
+    long long xi_stride;   // between the Xi triangles of the store
     double* out;
     int lmax;
     int dmax;

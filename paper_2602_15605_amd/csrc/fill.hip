@@ -58,7 +58,7 @@ fill_kernel(FillArgs a) {
     const int r0 = kT * I, c0 = kT * J;
     const int t = threadIdx.x;
     const long long ld = lmax + 1;
-    const long long xi_stride = tri_size(lmax);
+    const long long xi_stride = job.xi_stride;
     int last_src = -1;
 
     for (int o = 0; o < a.n_out; ++o) {
@@ -261,9 +261,10 @@ hipError_t launch_fill_jobs(const FillJob* jobs, int n_jobs, const int* spec_src
 }
 
 hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
-                       double* out, int xi, hipStream_t s) {
+                       double* out, int xi, hipStream_t s, const double* xi_src, long long xi_stride) {
     FillJob j;
-    j.xi = ctx->xi;
+    j.xi = xi_src ? xi_src : ctx->xi;
+    j.xi_stride = xi_src ? xi_stride : tri_size(lmax);
     j.out = out;
     j.lmax = lmax;
     j.dmax = dmax;
@@ -273,10 +274,10 @@ hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spe
 
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                       const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
-                      hipStream_t s) {
+                      hipStream_t s, const double* xi_src, long long xi_stride) {
     BinArgs a;
-    a.xi = ctx->xi;
-    a.xi_stride = tri_size(lmax);
+    a.xi = xi_src ? xi_src : ctx->xi;
+    a.xi_stride = xi_src ? xi_stride : tri_size(lmax);
     a.out = out;
     a.edges = bin_edges_dev;
     a.inline_edges = n_bins <= kInlineBins ? 1 : 0;

@@ -89,8 +89,25 @@ __global__ void scale_windows_kernel(const double* __restrict__ wtt, const doubl
     wpf[2 * stride + l] = (float)c;
 }
 
+// The windows of up to kBandMasks masks (NULL: spectrum not needed), one set
+// per blockIdx.y, into the context's window sets (the float32 copies are not
+// written: the multi-mask strip does not read them).
+struct MaskWindows {
+    const double* w[kBandMasks][3];
+};
+
+__global__ void scale_windows_masks_kernel(MaskWindows mw, int n, int stride, double* __restrict__ wp) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const int m = blockIdx.y;
+    const double f = (2.0 * l + 1.0) * kInv4Pi;
+    double* out = wp + 3LL * stride * m;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) out[(long long)x * stride + l] = mw.w[m][x] ? mw.w[m][x][l] * f : 0.0;
+}
+
 // Exponent of the suffix maximum of |W'_x| over each parity: one work-group per
-// (spectrum x, parity p), threads over contiguous runs of l3 = p + 2 i.  Each
+// (spectrum x, parity p) and window set (blockIdx.y), threads over contiguous runs of l3 = p + 2 i.  Each
 // run's maximum, a suffix maximum across the runs (Hillis-Steele in LDS), then
 // each run walked backwards.  The float32 strip kernels scale an item's
 // staged U by 2^-e at its first l3 (the largest |W'| it can meet then lies in
@@ -106,8 +123,9 @@ __global__ void __launch_bounds__(kExpThreads) window_exponents_kernel(const dou
     const int per = (cnt + kExpThreads - 1) / kExpThreads;
     const int t = threadIdx.x;
     const int i0 = min(cnt, t * per), i1 = min(cnt, i0 + per);
-    const double* w = wp + (long long)x * stride + p;
-    int* e = wexp + (long long)x * stride + p;
+    const long long set = 3LL * stride * blockIdx.y;     // window set (mask) of this work-group
+    const double* w = wp + set + (long long)x * stride + p;
+    int* e = wexp + set + (long long)x * stride + p;
     double m = 0.0;
     for (int i = i0; i < i1; ++i) m = fmax(m, fabs(w[2 * i]));
     s_max[t] = m;
@@ -141,6 +159,11 @@ struct StripArgs {
     int dmax;            // largest diagonal computed
     int band;            // dmax < lmax: items on a (block, diagonal) grid
     int l3_lo, l3_hi;
+    // strip_fp32c_masks_kernel: mask m's windows at wp + m wp_mask_stride (exponents
+    // likewise in wexp), its Xi triangles at xi + m xi_mask_stride
+    int n_masks;
+    int wp_mask_stride;
+    long long xi_mask_stride;
 };
 
 // Work item -> (d, A): the block of rows A .. A + B - 1 of diagonal d, aligned
@@ -150,13 +173,19 @@ struct StripArgs {
 // steps.  Returns false for an item that has no block.
 //   Whole triangle: level m = j + floor(d / B) holds (m + 1) B items with
 //   B m (m + 1) / 2 before it; trips fall with m, so longest run first.
-//   Band (dmax < lmax): item = j (dmax + 1) + d; the band bounds every trip.
+//   Band (dmax < lmax): phases of kBandPhase diagonals in order of d, each
+//   phase block by block; the band bounds every trip.
 template <int B>
 __device__ inline bool strip_item(const StripArgs& a, int item, int* d_out, int* A_out) {
     int d, j;
     if (a.band) {
-        j = item / (a.dmax + 1);
-        d = item - j * (a.dmax + 1);
+        // phase p holds diagonals p kBandPhase .. + w - 1 of all J blocks, block-major
+        const int J = (a.lmax + B) / B;
+        const int p = item / (J * kBandPhase);
+        const int w = min(kBandPhase, a.dmax + 1 - p * kBandPhase);
+        const int r = item - p * J * kBandPhase;
+        j = r / w;
+        d = p * kBandPhase + r - j * w;
     } else {
         int m = (int)((sqrtf(8.0f * (float)item / (float)B + 1.0f) - 1.0f) * 0.5f);
         while (B * (m + 1) * (m + 2) / 2 <= item) ++m;
@@ -679,6 +708,262 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32-compensated strip over up to four masks of one band-limited call.  The
+// masks share lmax, the band and the spectra, so P = g(l1-k) h(l1+d+k), N' and
+// the products P N' and P N'^2 of a term are the same for all of them: only
+// U_X(k) = W'_X(l3) g(k) g(d+k) differs.  One wave computes an item for all M
+// masks of the call, the shared factors once per term and then one FMA per
+// mask and spectrum, so the g/h windows and the N' expansion are staged and
+// formed once for the group.  Each mask's U is formed and scaled as in
+// strip_fp32c_kernel (its own suffix-maximum exponents), rounded once to
+// float32 and staged as one float4 lane per mask.  Accumulation per mask,
+// spectrum and row: G-term FMA blocks; with CP > G, CP/G block sums are added
+// plainly into a mid sum; every CP steps (and at a chunk's end) a Kahan step in
+// float32; the pair is combined, rescaled and unscaled in float64.  Even L only.
+template <int MODE, int M, int G, int CP>
+__global__ void __launch_bounds__(kWave)
+strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
+    constexpr int R = kStripR;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
+    constexpr bool TE = MODE == kModePol;
+    constexpr bool TTS = MODE != kModeEE;
+    constexpr bool MID = CP > G;
+    constexpr int KC = kStripChunkF32;
+    using W = Win<R, KC>;
+    constexpr int B = W::kB;
+    constexpr int RB = kStripRebase;
+    static_assert(MODE != kModeEB, "even L only");
+    static_assert(M >= 1 && M <= 4, "one float4 lane per mask");
+    static_assert(KC % RB == 0 && RB % G == 0 && G % R == 0 && CP % G == 0 && KC % CP == 0,
+                  "chunk must hold whole splits, blocks and Kahan periods");
+    __shared__ float s_g[W::kPhys];
+    __shared__ float s_h[W::kPhys];
+    __shared__ float4 s_ux[TTS ? KC : 1];
+    __shared__ float4 s_uy[TE ? KC : 1];
+    __shared__ float4 s_uz[POL ? KC : 1];
+    __shared__ float s_uw[POL ? KC : 1];
+
+    int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
+    if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
+    const int n_valid = a.lmax - d + 1;
+    const int blk_max = A + B - 1;
+    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+    const int lane = threadIdx.x;
+    const int l1_0 = A + R * lane;
+
+    float kt[R][M], kte[R][M], kee[R][M], ct[R][M], cte[R][M], cee[R][M];
+    float mt[R][M], mte[R][M], mee[R][M];
+    float gw[R], hw[R], qf[R], rf[R];
+    // T = c_s - (a + b - 1) and Q = T^2 - (2ab + 1) at the current split start
+    // c_s, exact, carried from split to split (strip_fp32c_kernel)
+    int tq[R];
+    long long q64[R];
+    int c_cur;
+    {
+        const int l3s = d + 2 * k_lo;
+        c_cur = l3s * (l3s + 1);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        qf[j] = rf[j] = 0.0f;
+        const long long l1 = l1_0 + j, l2 = l1 + d;
+        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+        const long long t = (long long)c_cur - (aa + bb - 1);
+        tq[j] = (int)t;
+        q64[j] = t * t - (2 * aa * bb + 1);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            kt[j][m] = kte[j][m] = kee[j][m] = ct[j][m] = cte[j][m] = cee[j][m] = 0.0f;
+            mt[j][m] = mte[j][m] = mee[j][m] = 0.0f;
+        }
+    }
+    // per-mask power-of-two scales at the item's first l3 (strip_fp32c_kernel)
+    const int l3f = min(d + 2 * k_lo, a.l3_hi);
+    int ex_tt[M], ex_tp[M], ex_pp[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int* we = a.wexp + (long long)m * a.wp_mask_stride;
+        const bool on = m < a.n_masks;
+        ex_tt[m] = on ? we[l3f] : 0;
+        ex_tp[m] = on ? we[a.wp_stride + l3f] : 0;
+        ex_pp[m] = on ? we[2 * a.wp_stride + l3f] : 0;
+    }
+
+    for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
+        const int kc = min(KC, k_hi - k0 + 1);
+        const int kc_r = (kc + G - 1) / G * G;           // staged U of steps kc .. kc_r - 1 is 0
+        __syncthreads();
+        const int g_base = A - k0 - KC + 1;
+        const int h_base = A + d + k0;
+        const int g_off = KC - kc_r;
+        for (int i = lane; i < B + kc_r - 1; i += kWave) {
+            const int eg = g_base + g_off + i, eh = h_base + i;
+            s_g[W::phys(g_off + i)] = (eg >= 0 && eg < a.g_len) ? gf[eg] : 0.0f;
+            s_h[W::phys(i)] = (eh >= 0 && eh < a.h_len) ? hf[eh] : 0.0f;
+        }
+        for (int st = lane; st < kc_r; st += kWave) {
+            float ux[4] = {0.0f, 0.0f, 0.0f, 0.0f}, uy[4] = {0.0f, 0.0f, 0.0f, 0.0f},
+                  uz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float uw = 0.0f;
+            if (st < kc) {
+                const int k = k0 + st;
+                const int l3 = d + 2 * k;
+                const int l3c = d + 2 * (k0 + st / RB * RB);    // l3 at this step's split
+                const double gg = a.g[k] * a.g[d + k];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (m >= a.n_masks) continue;
+                    const double* w = a.wp + (long long)m * a.wp_mask_stride;
+                    if (TTS) ux[m] = (float)ldexp(w[l3] * gg, -ex_tt[m]);
+                    if (TE) uy[m] = (float)ldexp(w[a.wp_stride + l3] * gg, -ex_tp[m]);
+                    if (POL) uz[m] = (float)ldexp(w[2 * a.wp_stride + l3] * gg, -ex_pp[m]);
+                }
+                if (POL) uw = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
+            }
+            if (TTS) s_ux[st] = make_float4(ux[0], ux[1], ux[2], ux[3]);
+            if (TE) s_uy[st] = make_float4(uy[0], uy[1], uy[2], uy[3]);
+            if (POL) {
+                s_uz[st] = make_float4(uz[0], uz[1], uz[2], uz[3]);
+                s_uw[st] = uw;
+            }
+        }
+        __syncthreads();
+
+        if (k0 == k_lo) {
+#pragma unroll
+            for (int j = 0; j < R - 1; ++j) gw[j] = s_g[W::phys(R * lane + j + KC)];
+            gw[R - 1] = 0.0f;
+            hw[0] = 0.0f;
+#pragma unroll
+            for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
+        }
+        const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
+        const float* ph = s_h + (R + 1) * lane + (R - 1);
+        for (int sb = 0; sb < kc_r; sb += G) {
+            if (POL && sb % RB == 0) {
+                // move (T, Q) to this split's c_s: Q(c + D) = Q + D T + D (T + D)
+                const int l3c = d + 2 * (k0 + sb);
+                const int cc = l3c * (l3c + 1);
+                const int Ds = cc - c_cur;
+                c_cur = cc;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    q64[j] += (long long)Ds * tq[j];
+                    tq[j] += Ds;
+                    q64[j] += (long long)Ds * tq[j];
+                    qf[j] = (float)(double)q64[j];
+                    rf[j] = 2.0f * (float)tq[j];
+                }
+            }
+            float bt[R][M], bte[R][M], bee[R][M];
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int m = 0; m < M; ++m) bt[j][m] = bte[j][m] = bee[j][m] = 0.0f;
+#pragma unroll
+            for (int q = 0; q < G / R; ++q, pg -= R + 1, ph += R + 1) {
+                const int s0 = sb + q * R;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+#pragma unroll
+                    for (int j = R - 1; j > 0; --j) gw[j] = gw[j - 1];
+                    gw[0] = pg[-u];
+#pragma unroll
+                    for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
+                    hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
+                    float4 x4 = {0.0f, 0.0f, 0.0f, 0.0f}, y4 = x4, z4 = x4;
+                    float w = 0.0f;
+                    if (TTS) x4 = s_ux[s0 + u];
+                    if (TE) y4 = s_uy[s0 + u];
+                    if (POL) {
+                        z4 = s_uz[s0 + u];
+                        w = s_uw[s0 + u];
+                    }
+                    const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ys[4] = {y4.x, y4.y, y4.z, y4.w},
+                                zs[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float P = gw[j] * hw[j];
+                        if (TTS)
+#pragma unroll
+                            for (int m = 0; m < M; ++m) bt[j][m] = __builtin_fmaf(xs[m], P, bt[j][m]);
+                        if (POL) {
+                            const float N = __builtin_fmaf(w, rf[j] + w, qf[j]);   // N' = Q + D (2T + D)
+                            const float y = P * N;
+                            if (TE)
+#pragma unroll
+                                for (int m = 0; m < M; ++m) bte[j][m] = __builtin_fmaf(ys[m], y, bte[j][m]);
+                            const float z = y * N;
+#pragma unroll
+                            for (int m = 0; m < M; ++m) bee[j][m] = __builtin_fmaf(zs[m], z, bee[j][m]);
+                        }
+                    }
+                }
+            }
+            if (MID) {
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        if (TTS) mt[j][m] += bt[j][m];
+                        if (TE) mte[j][m] += bte[j][m];
+                        if (POL) mee[j][m] += bee[j][m];
+                    }
+                if ((sb + G) % CP != 0 && sb + G < kc_r) continue;
+            }
+            // Kahan step of the mid sums (or the block sums) into the pairs
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (TTS) {
+                        const float v = MID ? mt[j][m] : bt[j][m];
+                        const float yv = v - ct[j][m];
+                        const float tv = kt[j][m] + yv;
+                        ct[j][m] = (tv - kt[j][m]) - yv;
+                        kt[j][m] = tv;
+                        mt[j][m] = 0.0f;
+                    }
+                    if (TE) {
+                        const float v = MID ? mte[j][m] : bte[j][m];
+                        const float yv = v - cte[j][m];
+                        const float tv = kte[j][m] + yv;
+                        cte[j][m] = (tv - kte[j][m]) - yv;
+                        kte[j][m] = tv;
+                        mte[j][m] = 0.0f;
+                    }
+                    if (POL) {
+                        const float v = MID ? mee[j][m] : bee[j][m];
+                        const float yv = v - cee[j][m];
+                        const float tv = kee[j][m] + yv;
+                        cee[j][m] = (tv - kee[j][m]) - yv;
+                        kee[j][m] = tv;
+                        mee[j][m] = 0.0f;
+                    }
+                }
+        }
+    }
+
+    const long long off = diag_offset(a.lmax, d);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int l1 = l1_0 + j;
+        if (l1 < 0 || l1 >= n_valid) continue;
+        const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (m >= a.n_masks) continue;
+            double* xm = a.xi + (long long)m * a.xi_mask_stride;
+            if (TTS) xm[off + l1] = ldexp((double)kt[j][m] - (double)ct[j][m], ex_tt[m]);
+            if (TE) xm[a.xi_stride + off + l1] = ldexp(sc * ((double)kte[j][m] - (double)cte[j][m]), ex_tp[m]);
+            if (POL)
+                xm[2 * a.xi_stride + off + l1] = ldexp((sc * sc) * ((double)kee[j][m] - (double)cee[j][m]), ex_pp[m]);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
@@ -689,9 +974,25 @@ hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const 
     return hipGetLastError();
 }
 
-hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s) {
-    hipLaunchKernelGGL(window_exponents_kernel, dim3(6), dim3(kExpThreads), 0, s, ctx->wp, n, 2 * ctx->lmax_max + 1,
+hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s, int n_masks) {
+    const int stride = 2 * ctx->lmax_max + 1;
+    hipLaunchKernelGGL(window_exponents_kernel, dim3(6, n_masks), dim3(kExpThreads), 0, s, ctx->wp, n, stride,
                        ctx->wexp);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const* wtt, const double* const* wtp,
+                                      const double* const* wpp, int n_masks, int n, hipStream_t s) {
+    if (n_masks < 1 || n_masks > kBandMasks) return hipErrorInvalidValue;
+    MaskWindows w;
+    for (int m = 0; m < kBandMasks; ++m) {
+        const bool on = m < n_masks;
+        w.w[m][0] = on && wtt ? wtt[m] : nullptr;
+        w.w[m][1] = on && wtp ? wtp[m] : nullptr;
+        w.w[m][2] = on && wpp ? wpp[m] : nullptr;
+    }
+    hipLaunchKernelGGL(scale_windows_masks_kernel, dim3((n + 255) / 256, n_masks), dim3(256), 0, s, w, n,
+                       2 * ctx->lmax_max + 1, ctx->wp);
     return hipGetLastError();
 }
 
@@ -791,6 +1092,52 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     }
     if (n4 > 0x7fffffffLL) return hipErrorInvalidValue;
     return launch_strip_modes<R>(ctx, a, lmax, mode, precision, n4, s);
+}
+
+int strip_masks_per_launch(int mode) {
+    return mode == kStripPolEE ? kMasksPolEE : mode == kStripPol ? kMasksPol : mode == kStripEB ? 1 : kBandMasks;
+}
+
+hipError_t launch_strip_masks(const couple_ctx* ctx, int lmax, int mode, int n_masks, int l3_lo, int l3_hi,
+                              long long xi_stride, hipStream_t s) {
+    if (n_masks < 1 || n_masks > strip_masks_per_launch(mode)) return hipErrorInvalidValue;
+    StripArgs a;
+    a.g = ctx->g_pad + kTablePad;
+    a.h = ctx->h_pad + kTablePad;
+    a.wp = ctx->wp;
+    a.wexp = ctx->wexp;
+    a.cl = ctx->cl;
+    a.xi = ctx->xi;
+    a.xi_stride = xi_stride;
+    a.wp_stride = 2 * ctx->lmax_max + 1;
+    a.g_len = ctx->lmax_max + 1;
+    a.h_len = 2 * ctx->lmax_max + 1;
+    a.lmax = lmax;
+    a.dmax = std::min(lmax, l3_hi);
+    a.l3_lo = l3_lo;
+    a.l3_hi = l3_hi;
+    a.band = a.dmax < lmax ? 1 : 0;
+    a.n_masks = n_masks;
+    a.wp_mask_stride = 3 * a.wp_stride;
+    a.xi_mask_stride = 3 * xi_stride;
+    const long long n_items = count_items(lmax, a.dmax, kWave * kStripR, a.band != 0);
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_items), block(kWave);
+    const float* gf = ctx->gf_pad + kTablePad;
+    const float* hf = ctx->hf_pad + kTablePad;
+    constexpr int G = kCompBlock, CP = kCompPeriod;
+    if (mode == kStripPolEE)
+        hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModePolEE, kMasksPolEE, G, CP>), grid, block, 0, s, a, gf, hf);
+    else if (mode == kStripPol)
+        hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModePol, kMasksPol, G, CP>), grid, block, 0, s, a, gf, hf);
+    else if (mode == kStripTT)
+        hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModeTT, kBandMasks, G, CP>), grid, block, 0, s, a, gf, hf);
+    else if (mode == kStripEE)
+        hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModeEE, kBandMasks, G, CP>), grid, block, 0, s, a, gf, hf);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace couple

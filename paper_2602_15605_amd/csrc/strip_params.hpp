@@ -25,9 +25,28 @@ constexpr int kStripRSmall = 2;
 constexpr long long kStripSmallItemsF32 = 8192;
 constexpr long long kStripSmallItemsF64 = 4096;
 
+// Band-limited grids run in phases of this many consecutive diagonals, the
+// phases in order of d and each phase block by block.  A diagonal's trip,
+// (l3_hi - d)/2 steps for all but its lowest-l1 block, falls with d, so the
+// phases run longest first; inside a phase, waves dispatched together share
+// their block's g and h windows.  Measured on the 10^4 / l3 <= 1000 band
+// (FP32C, FP64 strip per mask): 0.406 / 0.708 ms with all diagonals of a block
+// in turn, 0.394 / 0.707 diagonal by diagonal, 0.383 / 0.680 with 256-diagonal
+// phases and 0.377 / 0.677 with 64.
+constexpr int kBandPhase = 64;
+
 // l3 steps staged in LDS per chunk by the float64 and float32 strip kernels.
 constexpr int kStripChunkF64 = 256;
 constexpr int kStripChunkF32 = 256;
+// Masks per launch of the multi-mask float32 kernel: at most 4 (one float4
+// lane each).  Its sums take 16 VGPRs per mask and spectrum (four rows, block,
+// mid and Kahan pair), so TT + TE + EE takes two.  TT + EE with four masks
+// needs 236 VGPRs (two waves per SIMD, as the 14 KB of LDS would allow at
+// most 2.75): on the 8-mask 10^4 band it ran 1.75 ms against 2.18 ms with two
+// masks per launch (156 VGPRs, three waves).
+constexpr int kBandMasks = 4;
+constexpr int kMasksPolEE = 4;
+constexpr int kMasksPol = 2;
 
 // float32 strip kernel: steps per exact split of t = c - (a + b - 1).  Within
 // one split the staged D(k) = c(l3) - c(l3 at the split) is below

@@ -95,19 +95,52 @@ def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk, spectra):
         _say("band unbinned fp64 %s max rel err %.3e" % (s, err))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32c", TOL_FP32C)])
-def test_band_batched_equals_single(torch_gpu, ctx, precision, tol):
-    """A batched call gives, mask by mask, what single calls give (bitwise)."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+@pytest.mark.parametrize("spectra", [("TT", "TE", "EE", "BB"), ("TT", "EE", "BB"), ("TT",), ("EE", "BB"),
+                                     ("TT", "TE"), ("TT", "EE", "EB")])
+def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
+    """A batched call gives, mask by mask, what single calls give (bitwise),
+    binned and not, for 1 .. 9 masks.  In FP32C the batched call runs the
+    multi-mask strip (four masks per launch, two with TE; EB keeps one launch
+    per mask), whose per-mask arithmetic is that of the single-mask kernel."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     lmax, lo, hi = 700, 3, 250
     rng = np.random.default_rng(77)
-    Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(3)]
-    edges = [0, 2, 30, 100, 101, 400, 701]
-    Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws], [w[1] for w in Ws], [w[2] for w in Ws],
-                                    lmax, spectra=("TT", "TE", "EE", "BB"), precision=precision,
+    Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(9)]
+    singles = {}
+    for edges in (None, [0, 2, 30, 100, 101, 400, 701]):
+        for m in range(9):
+            singles[(edges is None, m)] = couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=spectra,
+                                                             precision=precision, bin_edges=edges)
+        for n in (1, 2, 3, 4, 5, 9):
+            Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws[:n]], [w[1] for w in Ws[:n]],
+                                            [w[2] for w in Ws[:n]], lmax, spectra=spectra, precision=precision,
+                                            bin_edges=edges)
+            for m in range(n):
+                assert torch.equal(Kb[m], singles[(edges is None, m)]), (n, m, edges is None)
+
+
+def test_workload4_batched_equals_single(torch_gpu, ctx):
+    """The 8-mask band workload (FP32C, binned): the multi-mask call equals
+    eight single calls bitwise, and its unbinned form (four masks of one
+    launch) equals single unbinned calls."""
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    masks = [synth.workload_windows(4, mask=m) for m in range(8)]
+    dW = [[torch.as_tensor(masks[m][s]).cuda() for m in range(8)] for s in range(3)]
+    edges = np.arange(0, WIDTH * NBIN + 1, WIDTH)
+    Kb = couple.couple_band_batched(ctx, 0, LCUT, dW[0], None, dW[2], LMAX, spectra=SPEC3, precision="fp32c",
                                     bin_edges=edges)
-    for m in range(3):
-        K1 = couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=("TT", "TE", "EE", "BB"), precision=precision,
+    for m in range(8):
+        K1 = couple.couple_band(ctx, 0, LCUT, dW[0][m], None, dW[2][m], LMAX, spectra=SPEC3, precision="fp32c",
                                 bin_edges=edges)
-        assert torch.equal(Kb[m], K1)
+        assert torch.equal(Kb[m], K1), m
+    del Kb
+    Ku = couple.couple_band_batched(ctx, 0, LCUT, dW[0][:4], None, dW[2][:4], LMAX, spectra=("TT", "EE"),
+                                    precision="fp32c")
+    for m in (0, 3):
+        K1 = couple.couple_band(ctx, 0, LCUT, dW[0][m], None, dW[2][m], LMAX, spectra=("TT", "EE"),
+                                precision="fp32c")
+        assert torch.equal(Ku[m], K1), m
+        del K1
