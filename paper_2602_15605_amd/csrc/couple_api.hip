@@ -402,7 +402,8 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
         Timed t(ctx, s, 0);
         e = couple::launch_scale_windows_masks(ctx, (spectra & COUPLE_TT) ? W_TT : nullptr,
                                                (spectra & COUPLE_TE) ? W_TP : nullptr,
-                                               (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n_masks, n, s);
+                                               (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n_masks, n,
+                                               nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
     {
@@ -412,7 +413,13 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
     if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
     {
         Timed t(ctx, s, 1);
-        e = couple::launch_strip_masks(ctx, lmax, strip_mode(spectra), n_masks, l3_lo, hi, stride, s);
+        int lm[couple::kBandMasks];
+        long long off[couple::kBandMasks];
+        for (int m = 0; m < n_masks; ++m) {
+            lm[m] = lmax;
+            off[m] = 3 * stride * m;
+        }
+        e = couple::launch_strip_masks(ctx, strip_mode(spectra), n_masks, lm, ctx->xi, off, l3_lo, hi, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
     int src[couple::kMaxOut];
@@ -503,6 +510,94 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
 }  // extern "C"
 
 namespace {
+
+// Batched FP32C full matrices (even L) through the multi-mask strip: masks in
+// order of lmax, descending; groups of strip_masks_per_launch consecutive
+// masks, one strip launch each over the grid of the group's largest lmax (a
+// smaller mask's terms outside its triangle are formed and not stored; its
+// windows are 0 beyond its 2 lmax).  Their Xi stores lie side by side in the
+// batched workspace when it is reserved for all of them, else in the
+// context's Xi workspace; one fill launch follows for the masks it holds.
+int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lmax_i, const double* const* W_TT,
+                 const double* const* W_TP, const double* const* W_PP, unsigned spectra, double* const* out,
+                 hipStream_t s) {
+    const int mode = strip_mode(spectra);
+    const int per = couple::strip_masks_per_launch(mode);
+    long long total = 0;
+    for (int m = 0; m < n_masks; ++m) total += 3 * couple::tri_size(lmax_i[m]);
+    double* buf = ctx->xi;
+    long long cap = 4 * couple::tri_size(ctx->lmax_max);
+    if (ctx->bws && (long long)(ctx->bws_bytes / sizeof(double)) >= total && total > cap) {
+        buf = static_cast<double*>(ctx->bws);
+        cap = (long long)(ctx->bws_bytes / sizeof(double));
+    }
+    int src[couple::kMaxOut];
+    const int n_out = output_sources(spectra, src);
+    const int xi_only = (spectra & COUPLE_XI) ? 1 : 0;
+    hipError_t e = hipSuccess;
+    int i = 0;
+    while (i < n_masks) {
+        couple::FillJob jobs[couple::kMaxFillJobs];
+        int n_jobs = 0;
+        long long used = 0;
+        while (i < n_masks && n_jobs < couple::kMaxFillJobs) {
+            int g = std::min({per, n_masks - i, couple::kMaxFillJobs - n_jobs});
+            auto need = [&](int k) {
+                long long b = 0;
+                for (int q = 0; q < k; ++q) b += 3 * couple::tri_size(lmax_i[sorted[i + q]]);
+                return b;
+            };
+            while (g > 0 && used + need(g) > cap) --g;
+            if (g == 0) break;
+            int lm[couple::kBandMasks], nm[couple::kBandMasks];
+            long long off[couple::kBandMasks];
+            const double *wt[couple::kBandMasks], *wtp[couple::kBandMasks], *wpp[couple::kBandMasks];
+            long long o = used;
+            for (int k = 0; k < g; ++k) {
+                const int m = sorted[i + k];
+                lm[k] = lmax_i[m];
+                nm[k] = 2 * lm[k] + 1;
+                off[k] = o;
+                o += 3 * couple::tri_size(lm[k]);
+                wt[k] = (spectra & COUPLE_TT) ? W_TT[m] : nullptr;
+                wtp[k] = (spectra & COUPLE_TE) ? W_TP[m] : nullptr;
+                wpp[k] = (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP[m] : nullptr;
+                couple::FillJob& j = jobs[n_jobs++];
+                j.xi = buf + off[k];
+                j.xi_stride = couple::tri_size(lm[k]);
+                j.out = out[m];
+                j.lmax = lm[k];
+                j.dmax = lm[k];
+                j.block0 = 0;
+            }
+            const int L = *std::max_element(lm, lm + g);
+            {
+                Timed t(ctx, s, 0);
+                e = couple::launch_scale_windows_masks(ctx, wt, wtp, wpp, g, 2 * L + 1, nm, s);
+            }
+            if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
+            {
+                Timed t(ctx, s, 0);
+                e = couple::launch_window_exponents(ctx, 2 * L + 1, s, g);
+            }
+            if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
+            {
+                Timed t(ctx, s, 1);
+                e = couple::launch_strip_masks(ctx, mode, g, lm, buf, off, 0, 2 * L, s);
+            }
+            if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
+            used = o;
+            i += g;
+        }
+        if (n_jobs == 0) return fail(ctx, COUPLE_EDEVICE, "no room for one mask's Xi");
+        {
+            Timed t(ctx, s, 2);
+            e = couple::launch_fill_jobs(jobs, n_jobs, src, n_out, xi_only, s);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "fill launch");
+    }
+    return COUPLE_OK;
+}
 
 // Sort masks by lmax (descending, stable) into column groups of 16.
 int make_plan(couple_ctx* ctx, int n_masks, const int* lmax_i, couple::BatchPlan* p, int* order) {
@@ -601,6 +696,13 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == COUPLE_FP32C && n_masks >= 2 && !(spectra & COUPLE_EB)) {
+        int sorted[couple::kMaxGroups * couple::kMaskGroup];
+        int n_sorted = 0;
+        for (int gi = 0; gi < p.n_groups; ++gi)
+            for (int m = 0; m < p.n_masks[gi]; ++m) sorted[n_sorted++] = order[gi * couple::kMaskGroup + m];
+        return matrix_masks(ctx, n_masks, sorted, lmax_i, W_TT, W_TP, W_PP, spectra, out, s);
+    }
     if (!mfma) {
         // float64 / float32-compensated: one couple_matrix per mask, back to back on s
         for (int m = 0; m < n_masks; ++m) {

@@ -79,8 +79,9 @@ hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const 
 // The windows of n_masks <= kBandMasks masks into the context's window sets
 // 0 .. n_masks - 1 (float64 only), for launch_strip_masks; wtt/wtp/wpp NULL
 // where the spectrum is not needed.
+// n_m[m] (NULL: all n): entries of mask m's windows to read, W' = 0 from there to n.
 hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const* wtt, const double* const* wtp,
-                                      const double* const* wpp, int n_masks, int n, hipStream_t s);
+                                      const double* const* wpp, int n_masks, int n, const int* n_m, hipStream_t s);
 // wexp[x][l3] = e with max |W'_x(l3')| over l3' = l3, l3 + 2, .. < n in [2^(e-1), 2^e)
 // (0 where that maximum is 0), for the float32 strip kernels' per-item scaling
 // for window sets 0 .. n_masks - 1
@@ -90,9 +91,10 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
 // Masks one launch_strip_masks call takes in a mode (1: the mode has no such kernel).
 int strip_masks_per_launch(int mode);
 // FP32C over masks 0 .. n_masks - 1 (n_masks <= strip_masks_per_launch) of the window sets,
-// even-L modes: mask m's Xi triangles (TT, TE, EE slots) at xi + 3 m xi_stride.
-hipError_t launch_strip_masks(const couple_ctx* ctx, int lmax, int mode, int n_masks, int l3_lo, int l3_hi,
-                              long long xi_stride, hipStream_t s);
+// even-L modes, l3 in [l3_lo, l3_hi]: mask m (lmax_m[m]) gets its Xi triangles
+// (TT, TE, EE slots) of diagonals 0 .. min(lmax_m[m], l3_hi) at xi + xi_off[m].
+hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int n_masks, const int* lmax_m, double* xi,
+                              const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s);
 
 // fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
 //   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE, 3 EB) output i comes from, n_out <= kMaxOut outputs.

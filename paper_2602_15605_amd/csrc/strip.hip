@@ -94,6 +94,7 @@ __global__ void scale_windows_kernel(const double* __restrict__ wtt, const doubl
 // written: the multi-mask strip does not read them).
 struct MaskWindows {
     const double* w[kBandMasks][3];
+    int n[kBandMasks];   // entries of mask m's windows to read; W' = 0 from there on
 };
 
 __global__ void scale_windows_masks_kernel(MaskWindows mw, int n, int stride, double* __restrict__ wp) {
@@ -102,8 +103,9 @@ __global__ void scale_windows_masks_kernel(MaskWindows mw, int n, int stride, do
     const int m = blockIdx.y;
     const double f = (2.0 * l + 1.0) * kInv4Pi;
     double* out = wp + 3LL * stride * m;
+    const bool in = l < mw.n[m];
 #pragma unroll
-    for (int x = 0; x < 3; ++x) out[(long long)x * stride + l] = mw.w[m][x] ? mw.w[m][x][l] * f : 0.0;
+    for (int x = 0; x < 3; ++x) out[(long long)x * stride + l] = (in && mw.w[m][x]) ? mw.w[m][x][l] * f : 0.0;
 }
 
 // Exponent of the suffix maximum of |W'_x| over each parity: one work-group per
@@ -160,10 +162,13 @@ struct StripArgs {
     int band;            // dmax < lmax: items on a (block, diagonal) grid
     int l3_lo, l3_hi;
     // strip_fp32c_masks_kernel: mask m's windows at wp + m wp_mask_stride (exponents
-    // likewise in wexp), its Xi triangles at xi + m xi_mask_stride
+    // likewise in wexp); its Xi triangles at xi + m_xi[m], m_stride[m] apart,
+    // for rows l1 <= m_lmax[m] - d (lmax is the largest m_lmax)
     int n_masks;
     int wp_mask_stride;
-    long long xi_mask_stride;
+    int m_lmax[kBandMasks];
+    long long m_xi[kBandMasks];
+    long long m_stride[kBandMasks];
 };
 
 // Work item -> (d, A): the block of rows A .. A + B - 1 of diagonal d, aligned
@@ -739,14 +744,17 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
                   "chunk must hold whole splits, blocks and Kahan periods");
     __shared__ float s_g[W::kPhys];
     __shared__ float s_h[W::kPhys];
-    __shared__ float4 s_ux[TTS ? KC : 1];
-    __shared__ float4 s_uy[TE ? KC : 1];
-    __shared__ float4 s_uz[POL ? KC : 1];
-    __shared__ float s_uw[POL ? KC : 1];
+    // a step's U packed into NV float4: slots x[m] = m, y[m] = NX + m, z[m] = NX + NY + m,
+    // then D (N' expansion) in slot NU when that fits the last float4, else in s_uw
+    constexpr int NX = TTS ? M : 0, NY = TE ? M : 0, NZ = POL ? M : 0;
+    constexpr int NU = NX + NY + NZ;
+    constexpr bool WPACK = POL && NU % 4 != 0;
+    constexpr int NV = (NU + (WPACK ? 1 : 0) + 3) / 4;
+    __shared__ float4 s_u4[KC][NV];
+    __shared__ float s_uw[(POL && !WPACK) ? KC : 1];
 
     int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
     if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
-    const int n_valid = a.lmax - d + 1;
     const int blk_max = A + B - 1;
     const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
     const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
@@ -804,8 +812,9 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
             s_h[W::phys(i)] = (eh >= 0 && eh < a.h_len) ? hf[eh] : 0.0f;
         }
         for (int st = lane; st < kc_r; st += kWave) {
-            float ux[4] = {0.0f, 0.0f, 0.0f, 0.0f}, uy[4] = {0.0f, 0.0f, 0.0f, 0.0f},
-                  uz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float uf[4 * NV];
+#pragma unroll
+            for (int i = 0; i < 4 * NV; ++i) uf[i] = 0.0f;
             float uw = 0.0f;
             if (st < kc) {
                 const int k = k0 + st;
@@ -816,18 +825,17 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
                 for (int m = 0; m < M; ++m) {
                     if (m >= a.n_masks) continue;
                     const double* w = a.wp + (long long)m * a.wp_mask_stride;
-                    if (TTS) ux[m] = (float)ldexp(w[l3] * gg, -ex_tt[m]);
-                    if (TE) uy[m] = (float)ldexp(w[a.wp_stride + l3] * gg, -ex_tp[m]);
-                    if (POL) uz[m] = (float)ldexp(w[2 * a.wp_stride + l3] * gg, -ex_pp[m]);
+                    if (TTS) uf[m] = (float)ldexp(w[l3] * gg, -ex_tt[m]);
+                    if (TE) uf[NX + m] = (float)ldexp(w[a.wp_stride + l3] * gg, -ex_tp[m]);
+                    if (POL) uf[NX + NY + m] = (float)ldexp(w[2 * a.wp_stride + l3] * gg, -ex_pp[m]);
                 }
                 if (POL) uw = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
             }
-            if (TTS) s_ux[st] = make_float4(ux[0], ux[1], ux[2], ux[3]);
-            if (TE) s_uy[st] = make_float4(uy[0], uy[1], uy[2], uy[3]);
-            if (POL) {
-                s_uz[st] = make_float4(uz[0], uz[1], uz[2], uz[3]);
-                s_uw[st] = uw;
-            }
+            if (WPACK) uf[NU] = uw;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                s_u4[st][v] = make_float4(uf[4 * v], uf[4 * v + 1], uf[4 * v + 2], uf[4 * v + 3]);
+            if (POL && !WPACK) s_uw[st] = uw;
         }
         __syncthreads();
 
@@ -873,16 +881,19 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
 #pragma unroll
                     for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
                     hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
-                    float4 x4 = {0.0f, 0.0f, 0.0f, 0.0f}, y4 = x4, z4 = x4;
-                    float w = 0.0f;
-                    if (TTS) x4 = s_ux[s0 + u];
-                    if (TE) y4 = s_uy[s0 + u];
-                    if (POL) {
-                        z4 = s_uz[s0 + u];
-                        w = s_uw[s0 + u];
+                    float uf[4 * NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const float4 q4 = s_u4[s0 + u][v];
+                        uf[4 * v] = q4.x;
+                        uf[4 * v + 1] = q4.y;
+                        uf[4 * v + 2] = q4.z;
+                        uf[4 * v + 3] = q4.w;
                     }
-                    const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ys[4] = {y4.x, y4.y, y4.z, y4.w},
-                                zs[4] = {z4.x, z4.y, z4.z, z4.w};
+                    const float w = !POL ? 0.0f : WPACK ? uf[WPACK ? NU : 0] : s_uw[s0 + u];
+                    const float* xs = uf;
+                    const float* ys = uf + NX;
+                    const float* zs = uf + NX + NY;
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const float P = gw[j] * hw[j];
@@ -946,20 +957,20 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
         }
     }
 
-    const long long off = diag_offset(a.lmax, d);
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int l1 = l1_0 + j;
-        if (l1 < 0 || l1 >= n_valid) continue;
-        const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+    for (int m = 0; m < M; ++m) {
+        if (m >= a.n_masks || d > a.m_lmax[m]) continue;
+        double* xm = a.xi + a.m_xi[m] + diag_offset(a.m_lmax[m], d);
+        const long long st = a.m_stride[m];
+        const int rows = a.m_lmax[m] - d + 1;            // this mask's rows of diagonal d
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            if (m >= a.n_masks) continue;
-            double* xm = a.xi + (long long)m * a.xi_mask_stride;
-            if (TTS) xm[off + l1] = ldexp((double)kt[j][m] - (double)ct[j][m], ex_tt[m]);
-            if (TE) xm[a.xi_stride + off + l1] = ldexp(sc * ((double)kte[j][m] - (double)cte[j][m]), ex_tp[m]);
-            if (POL)
-                xm[2 * a.xi_stride + off + l1] = ldexp((sc * sc) * ((double)kee[j][m] - (double)cee[j][m]), ex_pp[m]);
+        for (int j = 0; j < R; ++j) {
+            const int l1 = l1_0 + j;
+            if (l1 < 0 || l1 >= rows) continue;
+            const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            if (TTS) xm[l1] = ldexp((double)kt[j][m] - (double)ct[j][m], ex_tt[m]);
+            if (TE) xm[st + l1] = ldexp(sc * ((double)kte[j][m] - (double)cte[j][m]), ex_tp[m]);
+            if (POL) xm[2 * st + l1] = ldexp((sc * sc) * ((double)kee[j][m] - (double)cee[j][m]), ex_pp[m]);
         }
     }
 }
@@ -982,7 +993,7 @@ hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s, 
 }
 
 hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const* wtt, const double* const* wtp,
-                                      const double* const* wpp, int n_masks, int n, hipStream_t s) {
+                                      const double* const* wpp, int n_masks, int n, const int* n_m, hipStream_t s) {
     if (n_masks < 1 || n_masks > kBandMasks) return hipErrorInvalidValue;
     MaskWindows w;
     for (int m = 0; m < kBandMasks; ++m) {
@@ -990,6 +1001,7 @@ hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const
         w.w[m][0] = on && wtt ? wtt[m] : nullptr;
         w.w[m][1] = on && wtp ? wtp[m] : nullptr;
         w.w[m][2] = on && wpp ? wpp[m] : nullptr;
+        w.n[m] = on ? std::min(n, n_m ? n_m[m] : n) : 0;
     }
     hipLaunchKernelGGL(scale_windows_masks_kernel, dim3((n + 255) / 256, n_masks), dim3(256), 0, s, w, n,
                        2 * ctx->lmax_max + 1, ctx->wp);
@@ -1098,17 +1110,19 @@ int strip_masks_per_launch(int mode) {
     return mode == kStripPolEE ? kMasksPolEE : mode == kStripPol ? kMasksPol : mode == kStripEB ? 1 : kBandMasks;
 }
 
-hipError_t launch_strip_masks(const couple_ctx* ctx, int lmax, int mode, int n_masks, int l3_lo, int l3_hi,
-                              long long xi_stride, hipStream_t s) {
+hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int n_masks, const int* lmax_m, double* xi,
+                              const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s) {
     if (n_masks < 1 || n_masks > strip_masks_per_launch(mode)) return hipErrorInvalidValue;
+    int lmax = 0;
+    for (int m = 0; m < n_masks; ++m) lmax = std::max(lmax, lmax_m[m]);
     StripArgs a;
     a.g = ctx->g_pad + kTablePad;
     a.h = ctx->h_pad + kTablePad;
     a.wp = ctx->wp;
     a.wexp = ctx->wexp;
     a.cl = ctx->cl;
-    a.xi = ctx->xi;
-    a.xi_stride = xi_stride;
+    a.xi = xi;
+    a.xi_stride = 0;
     a.wp_stride = 2 * ctx->lmax_max + 1;
     a.g_len = ctx->lmax_max + 1;
     a.h_len = 2 * ctx->lmax_max + 1;
@@ -1119,7 +1133,13 @@ hipError_t launch_strip_masks(const couple_ctx* ctx, int lmax, int mode, int n_m
     a.band = a.dmax < lmax ? 1 : 0;
     a.n_masks = n_masks;
     a.wp_mask_stride = 3 * a.wp_stride;
-    a.xi_mask_stride = 3 * xi_stride;
+    for (int m = 0; m < kBandMasks; ++m) {
+        const bool on = m < n_masks;
+        a.m_lmax[m] = on ? lmax_m[m] : -1;
+        a.m_xi[m] = on ? xi_off[m] : 0;
+        // a mask's Xi triangles hold its diagonals 0 .. min(its lmax, l3_hi)
+        a.m_stride[m] = on ? diag_offset(lmax_m[m], std::min(lmax_m[m], l3_hi) + 1) : 0;
+    }
     const long long n_items = count_items(lmax, a.dmax, kWave * kStripR, a.band != 0);
     if (n_items <= 0) return hipSuccess;
     if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;

@@ -1,6 +1,7 @@
 """Batched form: many masks of uneven lmax in one call, contracted on the
-matrix cores (COUPLE_MFMA_FP32 and COUPLE_MFMA_BF16X3), checked per mask
-against the oracle.
+matrix cores (COUPLE_MFMA_FP32 and COUPLE_MFMA_BF16X3) or through the
+multi-mask FP32C strip, checked per mask against the oracle and, for the strip
+paths, bitwise against single-mask calls.
 
 The workload is 32 synthetic masks with lmax uniform in [500, 4000]; every
 mask is compared on >= 1% of its rows (at least 5, plus rows 0, 1, 2, lmax).
@@ -46,7 +47,7 @@ def _rand_windows(lmaxes, seed):
     return [[rng.uniform(0.05, 1.5, 2 * L + 1) for _ in range(3)] for L in lmaxes]
 
 
-@pytest.mark.parametrize("precision,tol", MFMA)
+@pytest.mark.parametrize("precision,tol", MFMA + [("fp32c", TOL_FP32C)])
 def test_batched_small_full_parity(torch_gpu, ctx, oracle_bulk, precision, tol):
     from paper_2602_15605_amd import couple
     torch = torch_gpu
@@ -99,16 +100,48 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, 
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
-def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision):
+@pytest.mark.parametrize("spectra", [SPEC4, ("TT", "EE", "BB"), ("TT",), ("EE", "BB"), ("TT", "TE"),
+                                     ("TT", "TE", "EE", "BB", "EB")])
+def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision, spectra):
+    """couple_matrix_batched in FP64 and FP32C equals couple_matrix mask by mask,
+    bitwise.  FP32C without EB runs the multi-mask strip: masks sorted by lmax,
+    two (TE) or four per launch over the grid of the group's largest lmax, so a
+    smaller mask's rows run in other blocks and past their own end; their sums
+    still come out bitwise equal (extra all-zero blocks leave k - c unchanged
+    through a Kahan step).  With 9 masks of mixed lmax (0, 1, equal values)."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
-    lmaxes = [40, 300, 7]
+    lmaxes = [40, 300, 7, 300, 128, 129, 255, 1, 0]
     Ws = _rand_windows(lmaxes, 8)
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
-    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision=precision)
-    for m in range(3):
-        K1 = couple.couple_matrix(ctx, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=SPEC4, precision=precision)
-        assert torch.equal(outs[m], K1)
+    outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=spectra, precision=precision)
+    for m in range(len(lmaxes)):
+        K1 = couple.couple_matrix(ctx, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=spectra, precision=precision)
+        assert torch.equal(outs[m], K1), (m, lmaxes[m])
+
+
+def test_batched_fp32c_xi_workspace_waves(torch_gpu, oracle_bulk):
+    """FP32C batched masks whose Xi stores exceed the context's Xi workspace and
+    no batched workspace: the call runs in waves of groups (here one mask per
+    group: two lmax-300 masks need 6 triangles, the workspace holds 4), each
+    followed by its fill; results equal single calls bitwise and the oracle."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [300, 300, 299, 150, 300]
+    c = couple.couple_init(300)
+    try:
+        Ws = _rand_windows(lmaxes, 9)
+        dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+        outs = couple.couple_matrix_batched(c, lmaxes, dW[0], dW[1], dW[2], spectra=SPEC4, precision="fp32c")
+        for m in range(len(lmaxes)):
+            K1 = couple.couple_matrix(c, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=SPEC4, precision="fp32c")
+            assert torch.equal(outs[m], K1), m
+        K = outs[4].cpu().numpy()
+    finally:
+        couple.couple_free(c)
+    Kr, Ar = oracle_bulk.coupling_rows(300, *Ws[4], spectra=SPEC4)
+    for i, s in enumerate(SPEC4):
+        assert_parity(K[i], Kr[i], Ar[i], TOL_FP32C, "waves %s" % s)
 
 
 def test_batched_errors(torch_gpu, ctx):
