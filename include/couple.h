@@ -166,15 +166,14 @@ int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const
                 const int *bin_edges, int n_bins, double *out, void *stream);
 
 /*
- * couple_band_batched -- couple_band for n_masks windows in one call.  In
- * COUPLE_FP32C without EB, up to four masks (two when TE is asked for) share
- * one strip launch: the g/h factors and the (-2 2 0) polynomial of each term
- * are formed once for them, and each mask's sums are those of couple_band
- * (the results are bitwise equal).  Such a group needs its Xi triangles of
- * diagonals 0 .. min(lmax, l3_hi) in the context's workspace, 3 per mask; the
- * group is cut to what fits, and where a single mask is left the per-mask
- * launches run.  Other precisions and EB: per-mask work back to back on
- * `stream`.
+ * couple_band_batched -- couple_band for n_masks windows in one call.  Without
+ * EB, up to four masks (two when TE is asked for) share one strip launch: the
+ * g/h factors and the (-2 2 0) polynomial of each term are formed once for
+ * them, and each mask's sums are those of couple_band (the results are
+ * bitwise equal, in COUPLE_FP64 and COUPLE_FP32C).  Such a group needs its Xi
+ * triangles of diagonals 0 .. min(lmax, l3_hi) in the context's workspace, 3
+ * per mask; the group is cut to what fits, and where a single mask is left the
+ * per-mask launches run.  With EB: per-mask work back to back on `stream`.
  *   W_TT, W_TP, W_PP : HOST arrays of n_masks DEVICE pointers (an array may
  *                      be NULL when no requested spectrum uses it).
  *   out              : device float64, n_masks consecutive outputs of the
@@ -220,7 +219,16 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *                     3j^2 tile on the matrix cores; needs
  *                     couple_reserve_batched first.  No allocation, no host
  *                     synchronisation: the call can be captured in a graph.
- *                     COUPLE_FP64 / COUPLE_FP32C -- couple_matrix per mask.
+ *                     COUPLE_FP64 / COUPLE_FP32C -- each mask's result is
+ *                     couple_matrix's, bitwise.  Without EB, masks sorted by
+ *                     lmax run in groups of four (two with TE) through one
+ *                     strip launch each, over the grid of the group's
+ *                     largest lmax, sharing each term's g/h factors and
+ *                     (-2 2 0) polynomial; their Xi stores go to the batched
+ *                     workspace when couple_reserve_batched sized it for the
+ *                     batch, else to the context's (in turns of what fits),
+ *                     and one fill launch follows per turn.  With EB:
+ *                     couple_matrix per mask.
  * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),
  * EDEVICE.
  */

@@ -377,12 +377,12 @@ int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const do
 // 0 .. dmax (three per mask, TT, TE and EE slots).
 int masks_per_launch(const couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, int lmax, unsigned spectra,
                      int precision) {
-    if (precision != COUPLE_FP32C || n_masks < 2 || (spectra & COUPLE_EB)) return 1;
+    if ((precision != COUPLE_FP32C && precision != COUPLE_FP64) || n_masks < 2 || (spectra & COUPLE_EB)) return 1;
     const int hi = std::min(l3_hi, 2 * lmax);
     if (l3_lo > hi) return 1;
     const long long band = couple::diag_offset(lmax, std::min(lmax, hi) + 1);
     const long long room = 4 * couple::tri_size(ctx->lmax_max) / (3 * band);
-    const int per = couple::strip_masks_per_launch(strip_mode(spectra));
+    const int per = couple::strip_masks_per_launch(strip_mode(spectra), precision);
     return (int)std::min<long long>({(long long)per, room, (long long)n_masks});
 }
 
@@ -391,7 +391,7 @@ int masks_per_launch(const couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, i
 // the strip writes each mask's Xi triangles (stride: diagonals 0 .. dmax) one
 // after the other, and each mask is filled or binned from its own.
 int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
-               const double* const* W_TP, const double* const* W_PP, int lmax, unsigned spectra,
+               const double* const* W_TP, const double* const* W_PP, int lmax, unsigned spectra, int precision,
                const int* bin_edges, int n_bins, double* out, size_t per_mask, hipStream_t s) {
     const int hi = std::min(l3_hi, 2 * lmax);
     const int dmax = std::min(lmax, hi);
@@ -406,7 +406,7 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
                                                nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
-    {
+    if (precision == COUPLE_FP32C) {
         Timed t(ctx, s, 0);
         e = couple::launch_window_exponents(ctx, n, s, n_masks);
     }
@@ -419,7 +419,7 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
             lm[m] = lmax;
             off[m] = 3 * stride * m;
         }
-        e = couple::launch_strip_masks(ctx, strip_mode(spectra), n_masks, lm, ctx->xi, off, l3_lo, hi, s);
+        e = couple::launch_strip_masks(ctx, strip_mode(spectra), precision, n_masks, lm, ctx->xi, off, l3_lo, hi, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
     int src[couple::kMaxOut];
@@ -492,8 +492,8 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
         for (int m0 = 0; m0 < n_masks; m0 += group) {
             const int g = std::min(group, n_masks - m0);
             rc = band_masks(ctx, g, l3_lo, l3_hi, need_tt ? W_TT + m0 : nullptr, need_tp ? W_TP + m0 : nullptr,
-                            need_pp ? W_PP + m0 : nullptr, lmax, spectra, bin_edges, n_bins, out + m0 * per_mask,
-                            per_mask, s);
+                            need_pp ? W_PP + m0 : nullptr, lmax, spectra, precision, bin_edges, n_bins,
+                            out + m0 * per_mask, per_mask, s);
             if (rc) return rc;
         }
         return COUPLE_OK;
@@ -519,10 +519,10 @@ namespace {
 // batched workspace when it is reserved for all of them, else in the
 // context's Xi workspace; one fill launch follows for the masks it holds.
 int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lmax_i, const double* const* W_TT,
-                 const double* const* W_TP, const double* const* W_PP, unsigned spectra, double* const* out,
-                 hipStream_t s) {
+                 const double* const* W_TP, const double* const* W_PP, unsigned spectra, int precision,
+                 double* const* out, hipStream_t s) {
     const int mode = strip_mode(spectra);
-    const int per = couple::strip_masks_per_launch(mode);
+    const int per = couple::strip_masks_per_launch(mode, precision);
     long long total = 0;
     for (int m = 0; m < n_masks; ++m) total += 3 * couple::tri_size(lmax_i[m]);
     double* buf = ctx->xi;
@@ -548,6 +548,10 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
                 return b;
             };
             while (g > 0 && used + need(g) > cap) --g;
+            // float64 forms N' by the group's largest lmax: keep a group on one side of kNarrowLmax
+            while (g > 1 && (lmax_i[sorted[i + g - 1]] > couple::kNarrowLmax) !=
+                                (lmax_i[sorted[i]] > couple::kNarrowLmax))
+                --g;
             if (g == 0) break;
             int lm[couple::kBandMasks], nm[couple::kBandMasks];
             long long off[couple::kBandMasks];
@@ -576,14 +580,14 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
                 e = couple::launch_scale_windows_masks(ctx, wt, wtp, wpp, g, 2 * L + 1, nm, s);
             }
             if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
-            {
+            if (precision == COUPLE_FP32C) {
                 Timed t(ctx, s, 0);
                 e = couple::launch_window_exponents(ctx, 2 * L + 1, s, g);
             }
             if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
             {
                 Timed t(ctx, s, 1);
-                e = couple::launch_strip_masks(ctx, mode, g, lm, buf, off, 0, 2 * L, s);
+                e = couple::launch_strip_masks(ctx, mode, precision, g, lm, buf, off, 0, 2 * L, s);
             }
             if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
             used = o;
@@ -696,12 +700,12 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (precision == COUPLE_FP32C && n_masks >= 2 && !(spectra & COUPLE_EB)) {
+    if ((precision == COUPLE_FP32C || precision == COUPLE_FP64) && n_masks >= 2 && !(spectra & COUPLE_EB)) {
         int sorted[couple::kMaxGroups * couple::kMaskGroup];
         int n_sorted = 0;
         for (int gi = 0; gi < p.n_groups; ++gi)
             for (int m = 0; m < p.n_masks[gi]; ++m) sorted[n_sorted++] = order[gi * couple::kMaskGroup + m];
-        return matrix_masks(ctx, n_masks, sorted, lmax_i, W_TT, W_TP, W_PP, spectra, out, s);
+        return matrix_masks(ctx, n_masks, sorted, lmax_i, W_TT, W_TP, W_PP, spectra, precision, out, s);
     }
     if (!mfma) {
         // float64 / float32-compensated: one couple_matrix per mask, back to back on s

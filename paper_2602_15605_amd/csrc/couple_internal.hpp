@@ -89,12 +89,12 @@ hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s, 
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,
                         int l3_hi, hipStream_t s);
 // Masks one launch_strip_masks call takes in a mode (1: the mode has no such kernel).
-int strip_masks_per_launch(int mode);
-// FP32C over masks 0 .. n_masks - 1 (n_masks <= strip_masks_per_launch) of the window sets,
+int strip_masks_per_launch(int mode, int precision);
+// FP32C or FP64 over masks 0 .. n_masks - 1 (n_masks <= strip_masks_per_launch) of the window sets,
 // even-L modes, l3 in [l3_lo, l3_hi]: mask m (lmax_m[m]) gets its Xi triangles
 // (TT, TE, EE slots) of diagonals 0 .. min(lmax_m[m], l3_hi) at xi + xi_off[m].
-hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int n_masks, const int* lmax_m, double* xi,
-                              const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s);
+hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, int n_masks, const int* lmax_m,
+                              double* xi, const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s);
 
 // fill / bin kernels (fill.hip); Xi exists for diagonals d <= dmax and is 0 beyond.
 //   spec_src[i] = which Xi (0 TT, 1 TE, 2 EE, 3 EB) output i comes from, n_out <= kMaxOut outputs.

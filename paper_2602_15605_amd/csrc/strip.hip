@@ -222,7 +222,7 @@ enum : int { kModeTT = 0, kModePol = 1, kModeEB = 2, kModePolEE = 3, kModeEE = 4
 // WIDE (lmax > kNarrowLmax): a(a-2) + b(b-2) exceeds 2^53 and N' cancels
 // against it when l1 << l2, so N' is taken as t^2 - (2ab + 1) with t exact and
 // 2ab + 1 = beta_hi + beta_lo split exactly: one more operation per term.
-constexpr int kNarrowLmax = 8000;
+// (kNarrowLmax: strip_params.hpp)
 
 template <int R, int MODE, bool WIDE>
 __global__ void __launch_bounds__(kWave)
@@ -975,6 +975,171 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
     }
 }
 
+// ---------------------------------------------------------------------------
+// Float64 strip over up to four masks of one call (strip_fp32c_masks_kernel's
+// layout and sharing: P, N', P N' and P N'^2 once per term, one FMA per mask
+// and spectrum).  Each mask's U and sums are those of strip_fp64_kernel: a
+// plain FMA chain per row in step order, so the chunk length (kStripChunkF64Masks
+// steps, short enough for the masks' float64 U to leave LDS for two waves per
+// SIMD) does not change a result bit.  Even L only.
+
+template <int MODE, int M, bool WIDE>
+__global__ void __launch_bounds__(kWave)
+strip_fp64_masks_kernel(StripArgs a) {
+    constexpr int R = kStripR;
+    constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
+    constexpr bool TE = MODE == kModePol;
+    constexpr bool TTS = MODE != kModeEE;
+    constexpr int KC = kStripChunkF64Masks;
+    using W = Win<R, KC>;
+    constexpr int B = W::kB;
+    static_assert(MODE != kModeEB, "even L only");
+    static_assert(M >= 1 && M <= kBandMasks, "masks per launch");
+    static_assert(KC % R == 0 && KC % kWave == 0, "chunk of whole step groups and lanes");
+    // a step's U in NV double2: slots x[m] = m, y[m] = NX + m, z[m] = NX + NY + m, then c
+    constexpr int NX = TTS ? M : 0, NY = TE ? M : 0, NZ = POL ? M : 0;
+    constexpr int NU = NX + NY + NZ + (POL ? 1 : 0);
+    constexpr int NV = (NU + 1) / 2;
+    __shared__ double s_g[W::kPhys];
+    __shared__ double s_h[W::kPhys];
+    __shared__ double2 s_u2[KC][NV];
+
+    int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
+    if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
+    const int blk_max = A + B - 1;
+    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+    const int lane = threadIdx.x;
+    const int l1_0 = A + R * lane;
+
+    // N' per row as in strip_fp64_kernel (narrow: c (c - gam2) + kap; WIDE: t^2 - kap - blo)
+    double tt[R][M], te[R][M], ee[R][M], gam2[R], kap[R], blo[R], gw[R], hw[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) tt[j][m] = te[j][m] = ee[j][m] = 0.0;
+        blo[j] = 0.0;
+        const long long l1 = l1_0 + j, l2 = l1 + d;
+        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+        if (WIDE) {
+            const long long beta = 2 * aa * bb + 1;
+            gam2[j] = (double)(aa + bb - 1);
+            kap[j] = (double)beta;
+            blo[j] = (double)(beta - (long long)kap[j]);
+        } else {
+            gam2[j] = (double)(2 * (aa + bb - 1));
+            kap[j] = (double)(aa * (aa - 2) + bb * (bb - 2));
+        }
+    }
+
+    for (int k0 = k_lo; k0 <= k_hi; k0 += KC) {
+        const int kc = min(KC, k_hi - k0 + 1);
+        const int kc_r = (kc + R - 1) / R * R;           // staged U of steps kc .. kc_r - 1 is 0
+        __syncthreads();
+        const int g_base = A - k0 - KC + 1;
+        const int h_base = A + d + k0;
+        const int g_off = KC - kc_r, n_win = B + kc_r - 1;
+        for (int i = lane; i < n_win; i += kWave) {
+            const int eg = g_base + g_off + i, eh = h_base + i;
+            s_g[W::phys(g_off + i)] = (eg >= 0 && eg < a.g_len) ? a.g[eg] : 0.0;
+            s_h[W::phys(i)] = (eh >= 0 && eh < a.h_len) ? a.h[eh] : 0.0;
+        }
+        for (int st = lane; st < kc_r; st += kWave) {
+            double uf[2 * NV];
+#pragma unroll
+            for (int i = 0; i < 2 * NV; ++i) uf[i] = 0.0;
+            if (st < kc) {
+                const int k = k0 + st;
+                const int l3 = d + 2 * k;
+                const double gg = a.g[k] * a.g[d + k];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (m >= a.n_masks) continue;
+                    const double* w = a.wp + (long long)m * a.wp_mask_stride;
+                    if (TTS) uf[m] = w[l3] * gg;
+                    if (TE) uf[NX + m] = w[a.wp_stride + l3] * gg;
+                    if (POL) uf[NX + NY + m] = w[2 * a.wp_stride + l3] * gg;
+                }
+                if (POL) uf[NU - 1] = (double)((long long)l3 * (l3 + 1));
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s_u2[st][v] = make_double2(uf[2 * v], uf[2 * v + 1]);
+        }
+        __syncthreads();
+
+        if (k0 == k_lo) {
+#pragma unroll
+            for (int j = 0; j < R - 1; ++j) gw[j] = s_g[W::phys(R * lane + j + KC)];
+            gw[R - 1] = 0.0;
+            hw[0] = 0.0;
+#pragma unroll
+            for (int j = 1; j < R; ++j) hw[j] = s_h[W::phys(R * lane + j - 1)];
+        }
+        const double* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
+        const double* ph = s_h + (R + 1) * lane + (R - 1);
+        for (int s0 = 0; s0 < kc_r; s0 += R, pg -= R + 1, ph += R + 1) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+#pragma unroll
+                for (int j = R - 1; j > 0; --j) gw[j] = gw[j - 1];
+                gw[0] = pg[-u];
+#pragma unroll
+                for (int j = 0; j < R - 1; ++j) hw[j] = hw[j + 1];
+                hw[R - 1] = ph[u + (u >= 1 ? 1 : 0)];
+                double uf[2 * NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double2 q2 = s_u2[s0 + u][v];
+                    uf[2 * v] = q2.x;
+                    uf[2 * v + 1] = q2.y;
+                }
+                const double c = POL ? uf[POL ? NU - 1 : 0] : 0.0;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const double P = gw[j] * hw[j];
+                    if (TTS)
+#pragma unroll
+                        for (int m = 0; m < M; ++m) tt[j][m] = __builtin_fma(uf[m], P, tt[j][m]);
+                    if (POL) {
+                        double N;
+                        if (WIDE) {
+                            const double t = c - gam2[j];
+                            N = __builtin_fma(t, t, -kap[j]) - blo[j];
+                        } else {
+                            const double dc = c - gam2[j];
+                            N = __builtin_fma(c, dc, kap[j]);
+                        }
+                        const double y = P * N;
+                        if (TE)
+#pragma unroll
+                            for (int m = 0; m < M; ++m) te[j][m] = __builtin_fma(uf[NX + m], y, te[j][m]);
+                        const double z = y * N;
+#pragma unroll
+                        for (int m = 0; m < M; ++m) ee[j][m] = __builtin_fma(uf[NX + NY + m], z, ee[j][m]);
+                    }
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (m >= a.n_masks || d > a.m_lmax[m]) continue;
+        double* xm = a.xi + a.m_xi[m] + diag_offset(a.m_lmax[m], d);
+        const long long st = a.m_stride[m];
+        const int rows = a.m_lmax[m] - d + 1;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int l1 = l1_0 + j;
+            if (l1 < 0 || l1 >= rows) continue;
+            const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            if (TTS) xm[l1] = tt[j][m];
+            if (TE) xm[st + l1] = sc * te[j][m];
+            if (POL) xm[2 * st + l1] = (sc * sc) * ee[j][m];
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_scale_windows(const couple_ctx* ctx, const double* wtt, const double* wtp,
@@ -1106,13 +1271,15 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
     return launch_strip_modes<R>(ctx, a, lmax, mode, precision, n4, s);
 }
 
-int strip_masks_per_launch(int mode) {
-    return mode == kStripPolEE ? kMasksPolEE : mode == kStripPol ? kMasksPol : mode == kStripEB ? 1 : kBandMasks;
+int strip_masks_per_launch(int mode, int precision) {
+    if (mode == kStripEB) return 1;
+    if (precision == COUPLE_FP64) return mode == kStripPolEE ? kMasksPolEEF64 : mode == kStripPol ? kMasksPolF64 : kBandMasks;
+    return mode == kStripPolEE ? kMasksPolEE : mode == kStripPol ? kMasksPol : kBandMasks;
 }
 
-hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int n_masks, const int* lmax_m, double* xi,
-                              const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s) {
-    if (n_masks < 1 || n_masks > strip_masks_per_launch(mode)) return hipErrorInvalidValue;
+hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, int n_masks, const int* lmax_m,
+                              double* xi, const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s) {
+    if (n_masks < 1 || n_masks > strip_masks_per_launch(mode, precision)) return hipErrorInvalidValue;
     int lmax = 0;
     for (int m = 0; m < n_masks; ++m) lmax = std::max(lmax, lmax_m[m]);
     StripArgs a;
@@ -1146,6 +1313,26 @@ hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int n_masks, cons
     const dim3 grid((unsigned)n_items), block(kWave);
     const float* gf = ctx->gf_pad + kTablePad;
     const float* hf = ctx->hf_pad + kTablePad;
+    if (precision == COUPLE_FP64) {
+        const bool wide = lmax > kNarrowLmax;
+        if (mode == kStripPolEE && wide)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModePolEE, kMasksPolEEF64, true>), grid, block, 0, s, a);
+        else if (mode == kStripPolEE)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModePolEE, kMasksPolEEF64, false>), grid, block, 0, s, a);
+        else if (mode == kStripPol && wide)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModePol, kMasksPolF64, true>), grid, block, 0, s, a);
+        else if (mode == kStripPol)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModePol, kMasksPolF64, false>), grid, block, 0, s, a);
+        else if (mode == kStripTT)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeTT, kBandMasks, false>), grid, block, 0, s, a);
+        else if (mode == kStripEE && wide)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeEE, kBandMasks, true>), grid, block, 0, s, a);
+        else if (mode == kStripEE)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeEE, kBandMasks, false>), grid, block, 0, s, a);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     constexpr int G = kCompBlock, CP = kCompPeriod;
     if (mode == kStripPolEE)
         hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModePolEE, kMasksPolEE, G, CP>), grid, block, 0, s, a, gf, hf);

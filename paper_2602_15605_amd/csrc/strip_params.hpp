@@ -47,11 +47,23 @@ constexpr int kStripChunkF32 = 256;
 constexpr int kBandMasks = 4;
 constexpr int kMasksPolEE = 4;
 constexpr int kMasksPol = 2;
+// The float64 multi-mask kernel (one float64 sum per mask, spectrum and row;
+// 248 VGPRs for TT + EE with four masks, two waves per SIMD).  On the 8-mask
+// 10^4 band (strip per call): 2.45 ms with four masks per launch and 128-step
+// chunks, 2.49 ms with 64-step chunks, 3.07 / 3.39 ms with three / two masks,
+// against 5.37 ms for one launch per mask.
+constexpr int kMasksPolEEF64 = 4;
+constexpr int kMasksPolF64 = 2;
+constexpr int kStripChunkF64Masks = 128;
 
 // float32 strip kernel: steps per exact split of t = c - (a + b - 1).  Within
 // one split the staged D(k) = c(l3) - c(l3 at the split) is below
 // 254 (2 l3 + 255) < 2^24 for l3 <= 2 x 16384, hence exact in float32.
 constexpr int kStripRebase = 128;
+
+// Above this lmax the float64 kernels form N' in the WIDE way (two more
+// exact pieces per row), since a(a-2) + b(b-2) no longer fits 2^53.
+constexpr int kNarrowLmax = 8000;
 
 // Zero guard band around the device copies of g(p) and 1/((2p+1)g(p)).
 constexpr int kTablePad = 64;
