@@ -121,6 +121,36 @@ def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
                 assert torch.equal(Kb[m], singles[(edges is None, m)]), (n, m, edges is None)
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_band_batched_steep_windows_equal_single(torch_gpu, ctx, oracle_bulk, precision):
+    """Masks with the l_c = 200..300 windows of the pol4_lmax2000 workload (W'_PP below
+    float32's normal range from l3 ~ 1790): each mask of a multi-mask launch keeps its
+    own FP32C scale exponents, so batched equals single calls bitwise, over the full
+    l3 range (the whole-triangle grid) and a band; one mask against the oracle."""
+    from paper_2602_15605_amd import couple, synth
+    torch = torch_gpu
+    lmax = 1000
+    Ws = [synth.workload_windows(1, mask=m, lmax=lmax) for m in range(5)]
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    for lo, hi in ((0, 2 * lmax), (0, 1900), (40, 700)):
+        Kb = couple.couple_band_batched(ctx, lo, hi, dW[0], dW[1], dW[2], lmax, spectra=("TT", "EE", "BB"),
+                                        precision=precision)
+        for m in range(5):
+            K1 = couple.couple_band(ctx, lo, hi, dW[0][m], dW[1][m], dW[2][m], lmax, spectra=("TT", "EE", "BB"),
+                                    precision=precision)
+            assert torch.equal(Kb[m], K1), (lo, hi, m)
+        if (lo, hi) == (0, 1900):
+            rows = np.array([0, 1, 2, 3, 500, 999, 1000])
+            got = Kb[4][:, torch.as_tensor(rows).cuda(), :].cpu().numpy()
+            Kr, Ar = oracle_bulk.coupling_rows(lmax, *Ws[4], rows=rows, spectra=("TT", "EE", "BB"),
+                                               l3_range=(lo, hi))
+            tol = TOL_FP32C if precision == "fp32c" else TOL_FP64
+            for i, sp in enumerate(("TT", "EE", "BB")):
+                assert_parity(got[i], Kr[i], Ar[i], tol, "steep %s %s" % (precision, sp))
+            assert np.all(got[:, 2:5, lmax - 2:] != 0.0)
+        del Kb
+
+
 def test_workload4_batched_equals_single(torch_gpu, ctx):
     """The 8-mask band workload (FP32C, binned): the multi-mask call equals
     eight single calls bitwise, and its unbinned form (four masks of one
