@@ -97,26 +97,28 @@ def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk, spectra):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 @pytest.mark.parametrize("spectra", [("TT", "TE", "EE", "BB"), ("TT", "EE", "BB"), ("TT",), ("EE", "BB"),
-                                     ("TT", "TE"), ("TT", "EE", "EB")])
+                                     ("TT", "TE"), ("TT", "EE", "EB"), ("TT", "EE", "BB", "XI")])
 def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
     """A batched call gives, mask by mask, what single calls give (bitwise),
-    binned and not, for 1 .. 9 masks.  In FP32C the batched call runs the
+    binned and not, K or Xi, for 1 .. 9 masks.  The batched call runs the
     multi-mask strip (four masks per launch, two with TE; EB keeps one launch
-    per mask), whose per-mask arithmetic is that of the single-mask kernel."""
+    per mask), whose per-mask arithmetic is that of the single-mask kernels."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     lmax, lo, hi = 700, 3, 250
+    xi = "XI" in spectra
+    spectra = tuple(s for s in spectra if s != "XI")
     rng = np.random.default_rng(77)
     Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(9)]
     singles = {}
     for edges in (None, [0, 2, 30, 100, 101, 400, 701]):
         for m in range(9):
             singles[(edges is None, m)] = couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=spectra,
-                                                             precision=precision, bin_edges=edges)
+                                                             precision=precision, bin_edges=edges, xi=xi)
         for n in (1, 2, 3, 4, 5, 9):
             Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws[:n]], [w[1] for w in Ws[:n]],
                                             [w[2] for w in Ws[:n]], lmax, spectra=spectra, precision=precision,
-                                            bin_edges=edges)
+                                            bin_edges=edges, xi=xi)
             for m in range(n):
                 assert torch.equal(Kb[m], singles[(edges is None, m)]), (n, m, edges is None)
 
