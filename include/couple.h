@@ -167,7 +167,8 @@ int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const
 
 /*
  * couple_band_batched -- couple_band for n_masks windows in one call.  Without
- * EB, up to four masks (two when TE is asked for) share one strip launch: the
+ * EB, up to four masks (three in FP32C, two in FP64 when TE is asked for)
+ * share one strip launch: the
  * g/h factors and the (-2 2 0) polynomial of each term are formed once for
  * them, and each mask's sums are those of couple_band (the results are
  * bitwise equal, in COUPLE_FP64 and COUPLE_FP32C).  Such a group needs its Xi
@@ -221,7 +222,8 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *                     synchronisation: the call can be captured in a graph.
  *                     COUPLE_FP64 / COUPLE_FP32C -- each mask's result is
  *                     couple_matrix's, bitwise.  Without EB, masks sorted by
- *                     lmax run in groups of four (two with TE) through one
+ *                     lmax run in groups of four (with TE three in FP32C,
+ *                     two in FP64) through one
  *                     strip launch each, over the grid of the group's
  *                     largest lmax, sharing each term's g/h factors and
  *                     (-2 2 0) polynomial; their Xi stores go to the batched

@@ -40,13 +40,14 @@ constexpr int kStripChunkF64 = 256;
 constexpr int kStripChunkF32 = 256;
 // Masks per launch of the multi-mask float32 kernel: at most 4 (one float4
 // lane each).  Its sums take 16 VGPRs per mask and spectrum (four rows, block,
-// mid and Kahan pair), so TT + TE + EE takes two.  TT + EE with four masks
-// needs 236 VGPRs (two waves per SIMD, as the 14 KB of LDS would allow at
-// most 2.75): on the 8-mask 10^4 band it ran 1.75 ms against 2.18 ms with two
-// masks per launch (156 VGPRs, three waves).
+// mid and Kahan pair).  TT + EE with four masks needs 230 VGPRs (two waves per
+// SIMD, as the 14 KB of LDS would allow at most 2.75): on the 8-mask 10^4 band
+// it ran 1.75 ms against 2.18 ms with two masks per launch (156 VGPRs, three
+// waves).  TT + TE + EE takes three (228 VGPRs; four would need 256, one
+// wave): the 32-mask batched call's strip ran 12.5 ms against 13.4 ms with two.
 constexpr int kBandMasks = 4;
 constexpr int kMasksPolEE = 4;
-constexpr int kMasksPol = 2;
+constexpr int kMasksPol = 3;
 // The float64 multi-mask kernel (one float64 sum per mask, spectrum and row;
 // 248 VGPRs for TT + EE with four masks, two waves per SIMD).  On the 8-mask
 // 10^4 band (strip per call): 2.45 ms with four masks per launch and 128-step

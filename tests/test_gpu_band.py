@@ -101,7 +101,7 @@ def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk, spectra):
 def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
     """A batched call gives, mask by mask, what single calls give (bitwise),
     binned and not, K or Xi, for 1 .. 9 masks.  The batched call runs the
-    multi-mask strip (four masks per launch, two with TE; EB keeps one launch
+    multi-mask strip (four masks per launch, fewer with TE; EB keeps one launch
     per mask), whose per-mask arithmetic is that of the single-mask kernels."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu

@@ -104,11 +104,12 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, 
                                      ("TT", "TE", "EE", "BB", "EB")])
 def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision, spectra):
     """couple_matrix_batched in FP64 and FP32C equals couple_matrix mask by mask,
-    bitwise.  FP32C without EB runs the multi-mask strip: masks sorted by lmax,
-    two (TE) or four per launch over the grid of the group's largest lmax, so a
-    smaller mask's rows run in other blocks and past their own end; their sums
-    still come out bitwise equal (extra all-zero blocks leave k - c unchanged
-    through a Kahan step).  With 9 masks of mixed lmax (0, 1, equal values)."""
+    bitwise.  Without EB it runs the multi-mask strip: masks sorted by lmax,
+    four per launch (with TE three in FP32C, two in FP64), over the grid of the
+    group's largest lmax, so a smaller mask's rows run in other blocks and past
+    their own end; their sums still come out bitwise equal (extra all-zero
+    blocks leave k - c unchanged through a Kahan step).  With 9 masks of mixed
+    lmax (0, 1, equal values)."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     lmaxes = [40, 300, 7, 300, 128, 129, 255, 1, 0]
