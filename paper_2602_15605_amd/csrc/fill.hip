@@ -127,9 +127,10 @@ struct BinArgs {
     int slot[kMaxOut];           // which distinct store output i reads
 };
 
-// One work-group per bin pair bb <= bc on a 2D grid (x: bc, y: bb; the blocks
-// with bb > bc return at once), so n_bins up to lmax_max + 1 stays within the
-// 32-bit work-item count of each grid dimension.  Xi(l1, l2) = Xi(l2, l1), so every element of the pair is read once,
+// One work-group per bin pair bb <= bc = bb + blockIdx.x on a 2D grid (x: the
+// offset, up to the widest reach of the band in bins; y: bb), so n_bins up to
+// lmax_max + 1 stays within the 32-bit work-item count of each grid dimension.
+// Pairs the band does not reach are zeroed before the launch.  Xi(l1, l2) = Xi(l2, l1), so every element of the pair is read once,
 // from the upper triangle (d = l2 - l1 >= 0, lanes over consecutive l1 of one
 // diagonal: contiguous in the packed store), and feeds both outputs:
 //   out[bb][bc] = (1/n_bb) sum (fs l2 + 1) Xi(l1, l2),
@@ -144,8 +145,8 @@ template <int NS>
 __global__ void __launch_bounds__(kBinThreads)
 bin_kernel(BinArgs a) {
     __shared__ double red[kBinWaves][2 * NS];
-    const int bb = blockIdx.y, bc = blockIdx.x;
-    if (bb > bc) return;
+    const int bb = blockIdx.y, bc = blockIdx.y + blockIdx.x;
+    if (bc >= a.n_bins) return;
     const int* E = a.inline_edges ? a.edges_in : a.edges;
     const int r_lo = E[bb], r_hi = E[bb + 1];
     const int c_lo = E[bc], c_hi = E[bc + 1];
@@ -296,7 +297,20 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
         if (k == a.n_src) a.src[a.n_src++] = spec_src[i];
         a.slot[i] = k;
     }
-    const dim3 grid((unsigned)n_bins, (unsigned)n_bins), block(kBinThreads);
+    // reach: the largest bc - bb of a pair with an element inside the band
+    // (E[bc] - (E[bb + 1] - 1) <= dmax); the bound is monotone in bb
+    const int* E = bin_edges_host;
+    int reach = 0;
+    for (int bb = 0, bc = 0; bb < n_bins; ++bb) {
+        if (bc < bb) bc = bb;
+        while (bc + 1 < n_bins && E[bc + 1] - (E[bb + 1] - 1) <= dmax) ++bc;
+        reach = std::max(reach, bc - bb);
+    }
+    if (reach + 1 < n_bins) {
+        const hipError_t e = launch_zero(out, (size_t)n_out * n_bins * n_bins, s);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)(reach + 1), (unsigned)n_bins), block(kBinThreads);
     switch (a.n_src) {
     case 1: hipLaunchKernelGGL(bin_kernel<1>, grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL(bin_kernel<2>, grid, block, 0, s, a); break;
