@@ -303,15 +303,15 @@ def run_extras(torch, couple, synth, args):
         out["band_lmax10000_cut1000_8masks_binned_" + prec] = {
             "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200,
             "kernel_ms_per_call": kms, "launches_per_call": {k: prof[k][1] / steps for k in kms},
-            "triples_per_mask": T_band, "flop_per_triple": FLOP_PER_TRIPLE_BAND,
-            "strip_tflops": tflops, "strip_roofline_frac": tflops / peak,
-            "executed_flop_per_mask_triple": executed, "strip_executed_tflops": xtflops,
-            "strip_executed_frac": xtflops / peak,
-            "note": ("two multi-mask strip launches of four masks (windows once per group), then one bin "
-                     "launch per mask; strip_tflops counts each mask's triples at the single-mask "
-                     "10 FLOP, so with the shared factors formed once per group it is a per-mask "
-                     "equivalent rate and can approach the peak; strip_executed_* count the FLOP "
-                     "actually executed")}
+            "triples_per_mask": T_band, "flop_per_triple_executed": executed,
+            "strip_tflops": xtflops, "strip_roofline_frac": xtflops / peak,
+            "flop_per_triple_single_mask": FLOP_PER_TRIPLE_BAND,
+            "strip_single_mask_equiv_tflops": tflops, "strip_single_mask_equiv_frac": tflops / peak,
+            "note": ("two multi-mask strip launches of four masks (windows once per group), then one zero and "
+                     "one bin launch per mask; strip_tflops / strip_roofline_frac count the FLOP executed "
+                     "(P, N' and the two products once per term for the group, 2 FMAs per mask); "
+                     "strip_single_mask_equiv_* charge every mask the single-mask 10 FLOP per triple, "
+                     "the rate one launch per mask would need to match")}
     # the same band-limited call writing the symmetric kernels Xi (the covariance kernels when
     # the windows are squared-mask spectra)
     ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, dW[0], None, dW[2], L,
