@@ -207,7 +207,7 @@ def test_autotune_and_tile_shapes(torch_gpu, ctx, oracle_bulk, precision, tol, s
         couple.couple_set_batched_tiles(ctx, *saved, precision=precision)
 
 
-@pytest.mark.parametrize("precision", ["mfma_fp32", "mfma_bf16x3"])
+@pytest.mark.parametrize("precision", ["mfma_fp32", "mfma_bf16x3", "fp32c", "fp64"])
 def test_batched_graph_replay(torch_gpu, ctx, precision):
     """The batched call is capture-safe: a captured graph replays to the eager result,
     replay after replay, with eager work in between."""
