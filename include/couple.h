@@ -230,7 +230,8 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *                     workspace when couple_reserve_batched sized it for the
  *                     batch, else to the context's (in turns of what fits),
  *                     and one fill launch follows per turn.  With EB:
- *                     couple_matrix per mask.
+ *                     couple_matrix per mask.  Kernels only, no allocation
+ *                     or host synchronisation: capturable in a graph.
  * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),
  * EDEVICE.
  */
