@@ -714,18 +714,20 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 }
 
 // ---------------------------------------------------------------------------
-// FP32-compensated strip over up to four masks of one band-limited call.  The
-// masks share lmax, the band and the spectra, so P = g(l1-k) h(l1+d+k), N' and
-// the products P N' and P N'^2 of a term are the same for all of them: only
-// U_X(k) = W'_X(l3) g(k) g(d+k) differs.  One wave computes an item for all M
-// masks of the call, the shared factors once per term and then one FMA per
-// mask and spectrum, so the g/h windows and the N' expansion are staged and
-// formed once for the group.  Each mask's U is formed and scaled as in
-// strip_fp32c_kernel (its own suffix-maximum exponents), rounded once to
-// float32 and staged as one float4 lane per mask.  Accumulation per mask,
-// spectrum and row: G-term FMA blocks; with CP > G, CP/G block sums are added
-// plainly into a mid sum; every CP steps (and at a chunk's end) a Kahan step in
-// float32; the pair is combined, rescaled and unscaled in float64.  Even L only.
+// FP32-compensated strip over up to four masks of one call.  The masks share
+// the band and the spectra, so P = g(l1-k) h(l1+d+k), N' and the products P N'
+// and P N'^2 of a term are the same for all of them: only U_X(k) =
+// W'_X(l3) g(k) g(d+k) differs.  One wave computes an item for all M masks,
+// the shared factors once per term and then one FMA per mask and spectrum, so
+// the g/h windows and the N' expansion are staged and formed once for the
+// group.  The grid is that of the largest lmax among the masks; a mask stores
+// only its own rows (l1 <= its lmax - d), and its windows are 0 above its
+// 2 lmax.  Each mask's U is formed and scaled as in strip_fp32c_kernel (its
+// own suffix-maximum exponents), rounded once to float32 and staged in packed
+// float4 slots.  Accumulation per mask, spectrum and row: G-term FMA blocks;
+// with CP > G, CP/G block sums are added plainly into a mid sum; every CP steps
+// (and at a chunk's end) a Kahan step in float32; the pair is combined,
+// rescaled and unscaled in float64.  Even L only.
 template <int MODE, int M, int G, int CP>
 __global__ void __launch_bounds__(kWave)
 strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
