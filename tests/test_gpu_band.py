@@ -153,6 +153,28 @@ def test_band_batched_steep_windows_equal_single(torch_gpu, ctx, oracle_bulk, pr
         del Kb
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+@pytest.mark.parametrize("lmax,lo,hi", [(0, 0, 0), (1, 0, 2), (2, 1, 3), (3, 0, 6), (5, 4, 4), (4, 9, 20)])
+def test_band_batched_tiny_equal_single(torch_gpu, ctx, precision, lmax, lo, hi):
+    """Tiny and empty bands through the batched call (multi-mask launches where
+    the band is non-empty, zeros where l3_lo > min(l3_hi, 2 lmax)), equal to single
+    calls bitwise, binned and not."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    rng = np.random.default_rng(5 + lmax)
+    n = max(2 * lmax + 1, hi + 1)
+    Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, n)).cuda() for _ in range(3)] for _ in range(5)]
+    spectra = ("TT", "TE", "EE", "BB")
+    for edges in (None, list(range(0, lmax + 2))):
+        Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws], [w[1] for w in Ws], [w[2] for w in Ws],
+                                        lmax, spectra=spectra, precision=precision, bin_edges=edges)
+        for m in range(5):
+            K1 = couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=spectra, precision=precision, bin_edges=edges)
+            assert torch.equal(Kb[m], K1), (m, edges is None)
+        if lo > min(hi, 2 * lmax):
+            assert not torch.any(Kb)
+
+
 def test_workload4_batched_equals_single(torch_gpu, ctx):
     """The 8-mask band workload (FP32C, binned): the multi-mask call equals
     eight single calls bitwise, and its unbinned form (four masks of one
