@@ -127,57 +127,56 @@ struct BinArgs {
     int slot[kMaxOut];           // which distinct store output i reads
 };
 
-// One work-group per bin pair bb <= bc = bb + blockIdx.x on a 2D grid (x: the
-// offset, up to the widest reach of the band in bins; y: bb), so n_bins up to
+// One work-group per row bin bb and two adjacent column bins bc0 = bb +
+// 2 blockIdx.x and bc1 = bc0 + 1 (when it exists) on a 2D grid (x: the offset
+// pair, up to the widest reach of the band in bins; y: bb), so n_bins up to
 // lmax_max + 1 stays within the 32-bit work-item count of each grid dimension.
-// Pairs the band does not reach are zeroed before the launch.  Xi(l1, l2) = Xi(l2, l1), so every element of the pair is read once,
-// from the upper triangle (d = l2 - l1 >= 0, lanes over consecutive l1 of one
-// diagonal: contiguous in the packed store), and feeds both outputs:
+// Pairs the band does not reach are zeroed before the launch.  Xi(l1, l2) =
+// Xi(l2, l1), so every element is read once, from the upper triangle
+// (d = l2 - l1 >= 0, lanes over consecutive l1 of one diagonal: contiguous in
+// the packed store; with two column bins a diagonal's run covers the whole
+// row bin), and feeds both outputs of its pair (bb, bc), bc = bc0 or bc1:
 //   out[bb][bc] = (1/n_bb) sum (fs l2 + 1) Xi(l1, l2),
 //   out[bc][bb] = (1/n_bc) sum (fs l1 + 1) Xi(l1, l2);
 // in a diagonal pair both sums land in out[bb][bb], the d = 0 elements once.
 // Outputs that share a Xi store (K^EE and K^BB) share its sums.  Each lane
 // sums its own elements in a fixed order, then the waves and the work-group
-// reduce in a fixed order, so the result does not depend on timing.  A pair
-// outside the band writes its two zeros and returns.  NS = the number of
-// distinct stores, so that only their sums take registers.
+// reduce in a fixed order, so the result does not depend on timing.  NS = the
+// number of distinct stores, so that only their sums take registers.
 template <int NS>
 __global__ void __launch_bounds__(kBinThreads)
 bin_kernel(BinArgs a) {
-    __shared__ double red[kBinWaves][2 * NS];
-    const int bb = blockIdx.y, bc = blockIdx.y + blockIdx.x;
-    if (bc >= a.n_bins) return;
+    __shared__ double red[kBinWaves][4 * NS];
+    const int bb = blockIdx.y, bc0 = blockIdx.y + 2 * blockIdx.x;
+    if (bc0 >= a.n_bins) return;
+    const bool two = bc0 + 1 < a.n_bins;
     const int* E = a.inline_edges ? a.edges_in : a.edges;
     const int r_lo = E[bb], r_hi = E[bb + 1];
-    const int c_lo = E[bc], c_hi = E[bc + 1];
+    const int c_lo = E[bc0], c_mid = E[bc0 + 1], c_hi = two ? E[bc0 + 2] : c_mid;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const double fs = a.xi_only ? 0.0 : 2.0;  // column factor fs l2 + 1
-    // d = l2 - l1 over the pair (the bins are ordered and disjoint: d >= 1 off the diagonal)
+    // d = l2 - l1 over both pairs (the bins are ordered and disjoint: d >= 1 off the diagonal)
     const int d_lo = max(c_lo - (r_hi - 1), 0);
     const int d_hi = min(c_hi - 1 - r_lo, a.dmax);
-    if (d_lo > d_hi) {
-        const int o = threadIdx.x;
-        if (o < a.n_out) {
-            double* out = a.out + (long long)o * a.n_bins * a.n_bins;
-            out[(long long)bb * a.n_bins + bc] = 0.0;
-            out[(long long)bc * a.n_bins + bb] = 0.0;
-        }
-        return;
-    }
-    double sa[NS], sb[NS];
+    // sums [0]: pair (bb, bc0), [1]: pair (bb, bc1); a: row-bin orientation, b: mirrored
+    double sa[2][NS], sb[2][NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sa[s] = sb[s] = 0.0;
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) sa[q][s] = sb[q][s] = 0.0;
     for (int l1c = r_lo; l1c < r_hi; l1c += kWave) {
-        // the diagonals that meet rows l1c .. l1c + 63 of this row bin inside the column bin
+        // the diagonals that meet rows l1c .. l1c + 63 of this row bin inside the column bins
         const int row_end = min(l1c + kWave, r_hi);
         const int dk_lo = max(d_lo, c_lo - (row_end - 1)), dk_hi = min(d_hi, c_hi - 1 - l1c);
         const int l1 = l1c + lane;
         for (int d0 = dk_lo + wave; d0 <= dk_hi; d0 += kBinWaves * kBinUnroll) {
             double x[kBinUnroll][NS], wa[kBinUnroll], wb[kBinUnroll];
+            bool hi_bin[kBinUnroll];
 #pragma unroll
             for (int u = 0; u < kBinUnroll; ++u) {
                 const int d = d0 + u * kBinWaves, l2 = l1 + d;
                 const bool ok = d <= dk_hi && l1 < row_end && l2 >= c_lo && l2 < c_hi;
+                hi_bin[u] = l2 >= c_mid;
                 wa[u] = ok ? fs * l2 + 1.0 : 0.0;
                 wb[u] = (ok && d > 0) ? fs * l1 + 1.0 : 0.0;
                 const long long off = ok ? diag_offset(a.lmax, d) + l1 : 0;
@@ -186,44 +185,54 @@ bin_kernel(BinArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < kBinUnroll; ++u) {
+                const double wa0 = hi_bin[u] ? 0.0 : wa[u], wa1 = hi_bin[u] ? wa[u] : 0.0;
+                const double wb0 = hi_bin[u] ? 0.0 : wb[u], wb1 = hi_bin[u] ? wb[u] : 0.0;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    sa[s] = __builtin_fma(wa[u], x[u][s], sa[s]);
-                    sb[s] = __builtin_fma(wb[u], x[u][s], sb[s]);
+                    sa[0][s] = __builtin_fma(wa0, x[u][s], sa[0][s]);
+                    sb[0][s] = __builtin_fma(wb0, x[u][s], sb[0][s]);
+                    sa[1][s] = __builtin_fma(wa1, x[u][s], sa[1][s]);
+                    sb[1][s] = __builtin_fma(wb1, x[u][s], sb[1][s]);
                 }
             }
         }
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            sa[s] += __shfl_down(sa[s], off, kWave);
-            sb[s] += __shfl_down(sb[s], off, kWave);
-        }
-    }
-    if (lane == 0) {
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            red[wave][2 * s] = sa[s];
-            red[wave][2 * s + 1] = sb[s];
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                sa[q][s] += __shfl_down(sa[q][s], off, kWave);
+                sb[q][s] += __shfl_down(sb[q][s], off, kWave);
+            }
         }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                red[wave][4 * s + 2 * q] = sa[q][s];
+                red[wave][4 * s + 2 * q + 1] = sb[q][s];
+            }
     }
     __syncthreads();
-    const int o = threadIdx.x;
-    if (o < a.n_out) {
+    const int o = threadIdx.x % kMaxOut, q = threadIdx.x / kMaxOut;   // output o of pair (bb, bc0 + q)
+    if (o < a.n_out && q < (two ? 2 : 1)) {
         const int s = a.slot[o];
+        const int bc = bc0 + q;
         double A = 0.0, B = 0.0;
         for (int w = 0; w < kBinWaves; ++w) {
-            A += red[w][2 * s];
-            B += red[w][2 * s + 1];
+            A += red[w][4 * s + 2 * q];
+            B += red[w][4 * s + 2 * q + 1];
         }
         double* out = a.out + (long long)o * a.n_bins * a.n_bins;
+        const int n_bc = E[bc + 1] - E[bc];
         if (bb == bc) {
             out[(long long)bb * a.n_bins + bb] = (A + B) / (double)(r_hi - r_lo);
         } else {
             out[(long long)bb * a.n_bins + bc] = A / (double)(r_hi - r_lo);
-            out[(long long)bc * a.n_bins + bb] = B / (double)(c_hi - c_lo);
+            out[(long long)bc * a.n_bins + bb] = B / (double)n_bc;
         }
     }
 }
@@ -310,7 +319,7 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
         const hipError_t e = launch_zero(out, (size_t)n_out * n_bins * n_bins, s);
         if (e != hipSuccess) return e;
     }
-    const dim3 grid((unsigned)(reach + 1), (unsigned)n_bins), block(kBinThreads);
+    const dim3 grid((unsigned)((reach + 2) / 2), (unsigned)n_bins), block(kBinThreads);
     switch (a.n_src) {
     case 1: hipLaunchKernelGGL(bin_kernel<1>, grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL(bin_kernel<2>, grid, block, 0, s, a); break;
