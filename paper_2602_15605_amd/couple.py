@@ -233,7 +233,9 @@ def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT"
                         precision="fp64", bin_edges=None, out=None, stream=None, xi=False):
     """couple_band for a list of masks: ``W_*`` are lists of GPU tensors (or None).
 
-    Returns [n_masks, n_spec, ...] with the couple_band layout per mask.
+    Returns [n_masks, n_spec, ...] with the couple_band layout per mask.  Without
+    EB the masks share strip launches (up to four per launch); every mask's
+    result is bitwise that of couple_band.
     """
     import torch
     bits = _spectra_bits(spectra, xi)
@@ -274,6 +276,10 @@ def couple_matrix_batched(ctx, lmax_list, W_TT, W_TP, W_PP, spectra=("TT", "TE",
 
     ``W_*`` are lists of float64 GPU tensors (or None); returns a list of
     [n_spec, lmax_m+1, lmax_m+1] tensors (Xi_X with ``xi=True``).
+    ``precision``: "mfma_fp32" / "mfma_bf16x3" contract on the matrix cores
+    (couple_reserve_batched first); "fp32c" / "fp64" run the multi-mask strip
+    (masks sorted by lmax share launches), each mask bitwise equal to
+    couple_matrix.
     """
     import torch
     bits = _spectra_bits(spectra, xi)
