@@ -425,13 +425,25 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
     int src[couple::kMaxOut];
     const int n_out = output_sources(spectra, src);
     const int xi = (spectra & COUPLE_XI) ? 1 : 0;
-    for (int m = 0; m < n_masks && e == hipSuccess; ++m) {
+    if (bin_edges) {
+        // one zero and one bin launch for the group's masks (outputs per_mask apart)
         Timed t(ctx, s, 2);
-        const double* xm = ctx->xi + 3 * stride * m;
-        double* om = out + m * per_mask;
-        e = bin_edges ? couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, om, xi, s,
-                                           xm, stride)
-                      : couple::launch_fill(ctx, lmax, dmax, src, n_out, om, xi, s, xm, stride);
+        e = couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, xi, s, ctx->xi,
+                               stride, n_masks, 3 * stride);
+    }
+    if (!bin_edges) {
+        // one fill launch for the group's masks
+        couple::FillJob jobs[couple::kBandMasks];
+        for (int m = 0; m < n_masks; ++m) {
+            jobs[m].xi = ctx->xi + 3 * stride * m;
+            jobs[m].xi_stride = stride;
+            jobs[m].out = out + m * per_mask;
+            jobs[m].lmax = lmax;
+            jobs[m].dmax = dmax;
+            jobs[m].block0 = 0;
+        }
+        Timed t(ctx, s, 2);
+        e = couple::launch_fill_jobs(jobs, n_masks, src, n_out, xi, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, bin_edges ? "bin launch" : "fill launch");
     return COUPLE_OK;

@@ -107,9 +107,12 @@ hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spe
 // Up to kInlineBins bins the edges travel in the kernel arguments (no upload,
 // nothing to synchronise); longer lists are read from bin_edges_dev.
 constexpr int kInlineBins = 512;
+//   n_masks: masks binned by the one launch, their Xi stores xi_mask_stride apart
+//   and their outputs n_out n_bins^2 apart.
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                       const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
-                      hipStream_t s, const double* xi_src = nullptr, long long xi_stride = 0);
+                      hipStream_t s, const double* xi_src = nullptr, long long xi_stride = 0, int n_masks = 1,
+                      long long xi_mask_stride = 0);
 // One fill job: Xi store [3][tri(lmax)] (Xi for diagonals d <= dmax, 0 beyond)
 // and its n_out output matrices [n_out][lmax+1][lmax+1].  block0 is set by
 // launch_fill_jobs.

@@ -113,7 +113,9 @@ constexpr int kBinUnroll = 4;    // diagonals per wave with their loads in fligh
 struct BinArgs {
     const double* xi;
     long long xi_stride;
+    long long xi_mask_stride;    // between the Xi stores of consecutive masks (blockIdx.z)
     double* out;
+    long long out_mask_stride;   // between the outputs of consecutive masks
     const int* edges;            // device copy of n_bins + 1 edges (when n_bins > kInlineBins)
     int inline_edges;            // edges are in edges_in
     int edges_in[kInlineBins + 1];
@@ -147,6 +149,9 @@ template <int NS>
 __global__ void __launch_bounds__(kBinThreads)
 bin_kernel(BinArgs a) {
     __shared__ double red[kBinWaves][4 * NS];
+    // mask blockIdx.z of the launch (locals: the argument block stays read-only)
+    const double* __restrict__ xis = a.xi + a.xi_mask_stride * blockIdx.z;
+    double* __restrict__ outs = a.out + a.out_mask_stride * blockIdx.z;
     const int bb = blockIdx.y, bc0 = blockIdx.y + 2 * blockIdx.x;
     if (bc0 >= a.n_bins) return;
     const bool two = bc0 + 1 < a.n_bins;
@@ -181,7 +186,7 @@ bin_kernel(BinArgs a) {
                 wb[u] = (ok && d > 0) ? fs * l1 + 1.0 : 0.0;
                 const long long off = ok ? diag_offset(a.lmax, d) + l1 : 0;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) x[u][s] = ok ? a.xi[(long long)a.src[s] * a.xi_stride + off] : 0.0;
+                for (int s = 0; s < NS; ++s) x[u][s] = ok ? xis[(long long)a.src[s] * a.xi_stride + off] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kBinUnroll; ++u) {
@@ -226,7 +231,7 @@ bin_kernel(BinArgs a) {
             A += red[w][4 * s + 2 * q];
             B += red[w][4 * s + 2 * q + 1];
         }
-        double* out = a.out + (long long)o * a.n_bins * a.n_bins;
+        double* out = outs + (long long)o * a.n_bins * a.n_bins;
         const int n_bc = E[bc + 1] - E[bc];
         if (bb == bc) {
             out[(long long)bb * a.n_bins + bb] = (A + B) / (double)(r_hi - r_lo);
@@ -284,11 +289,15 @@ hipError_t launch_fill(const couple_ctx* ctx, int lmax, int dmax, const int* spe
 
 hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec_src, int n_out,
                       const int* bin_edges_host, const int* bin_edges_dev, int n_bins, double* out, int xi,
-                      hipStream_t s, const double* xi_src, long long xi_stride) {
+                      hipStream_t s, const double* xi_src, long long xi_stride, int n_masks,
+                      long long xi_mask_stride) {
+    if (n_masks < 1 || n_masks > 65535) return hipErrorInvalidValue;
     BinArgs a;
     a.xi = xi_src ? xi_src : ctx->xi;
     a.xi_stride = xi_src ? xi_stride : tri_size(lmax);
+    a.xi_mask_stride = xi_mask_stride;
     a.out = out;
+    a.out_mask_stride = (long long)n_out * n_bins * n_bins;
     a.edges = bin_edges_dev;
     a.inline_edges = n_bins <= kInlineBins ? 1 : 0;
     for (int i = 0; i <= kInlineBins; ++i) a.edges_in[i] = (a.inline_edges && i <= n_bins) ? bin_edges_host[i] : 0;
@@ -316,10 +325,10 @@ hipError_t launch_bin(const couple_ctx* ctx, int lmax, int dmax, const int* spec
         reach = std::max(reach, bc - bb);
     }
     if (reach + 1 < n_bins) {
-        const hipError_t e = launch_zero(out, (size_t)n_out * n_bins * n_bins, s);
+        const hipError_t e = launch_zero(out, (size_t)n_masks * n_out * n_bins * n_bins, s);
         if (e != hipSuccess) return e;
     }
-    const dim3 grid((unsigned)((reach + 2) / 2), (unsigned)n_bins), block(kBinThreads);
+    const dim3 grid((unsigned)((reach + 2) / 2), (unsigned)n_bins, (unsigned)n_masks), block(kBinThreads);
     switch (a.n_src) {
     case 1: hipLaunchKernelGGL(bin_kernel<1>, grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL(bin_kernel<2>, grid, block, 0, s, a); break;
