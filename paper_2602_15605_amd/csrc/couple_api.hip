@@ -389,7 +389,7 @@ int masks_per_launch(const couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, i
 // n_masks (<= kBandMasks) masks of a batched band call in one strip launch:
 // their windows are scaled into the context's window sets 0 .. n_masks - 1,
 // the strip writes each mask's Xi triangles (stride: diagonals 0 .. dmax) one
-// after the other, and each mask is filled or binned from its own.
+// after the other, and one bin (or fill) launch serves every mask of the group.
 int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
                const double* const* W_TP, const double* const* W_PP, int lmax, unsigned spectra, int precision,
                const int* bin_edges, int n_bins, double* out, size_t per_mask, hipStream_t s) {
@@ -430,8 +430,7 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
         Timed t(ctx, s, 2);
         e = couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, xi, s, ctx->xi,
                                stride, n_masks, 3 * stride);
-    }
-    if (!bin_edges) {
+    } else {
         // one fill launch for the group's masks
         couple::FillJob jobs[couple::kBandMasks];
         for (int m = 0; m < n_masks; ++m) {
