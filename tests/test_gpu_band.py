@@ -175,6 +175,29 @@ def test_band_batched_tiny_equal_single(torch_gpu, ctx, precision, lmax, lo, hi)
             assert not torch.any(Kb)
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_band_batched_many_bins_equal_single(torch_gpu, ctx, precision):
+    """More bins than travel inline (edges uploaded to the device) through the
+    multi-mask bin launch: 5 masks, lmax 700, unit bins (701), band 0 .. 300."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmax, lo, hi = 700, 0, 300
+    rng = np.random.default_rng(17)
+    Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(5)]
+    edges = list(range(0, lmax + 2))
+    spectra = ("TT", "EE", "BB")
+    Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws], None, [w[2] for w in Ws], lmax,
+                                    spectra=spectra, precision=precision, bin_edges=edges)
+    assert Kb.shape == (5, 3, lmax + 1, lmax + 1)
+    for m in range(5):
+        K1 = couple.couple_band(ctx, lo, hi, Ws[m][0], None, Ws[m][2], lmax, spectra=spectra, precision=precision,
+                                bin_edges=edges)
+        assert torch.equal(Kb[m], K1), m
+    # unit bins: the binned matrices are K itself
+    K = couple.couple_band(ctx, lo, hi, Ws[1][0], None, Ws[1][2], lmax, spectra=spectra, precision=precision)
+    assert torch.allclose(Kb[1], K, rtol=1e-13, atol=0.0)
+
+
 def test_workload4_batched_equals_single(torch_gpu, ctx):
     """The 8-mask band workload (FP32C, binned): the multi-mask call equals
     eight single calls bitwise, and its unbinned form (four masks of one
