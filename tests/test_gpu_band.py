@@ -198,26 +198,27 @@ def test_band_batched_many_bins_equal_single(torch_gpu, ctx, precision):
     assert torch.allclose(Kb[1], K, rtol=1e-13, atol=0.0)
 
 
-def test_workload4_batched_equals_single(torch_gpu, ctx):
-    """The 8-mask band workload (FP32C, binned): the multi-mask call equals
-    eight single calls bitwise, and its unbinned form (four masks of one
-    launch) equals single unbinned calls."""
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_workload4_batched_equals_single(torch_gpu, ctx, precision):
+    """The 8-mask band workload (binned): the multi-mask call equals eight
+    single calls bitwise, and its unbinned form (four masks of one launch)
+    equals single unbinned calls.  lmax = 10^4 takes the wide float64 N'."""
     from paper_2602_15605_amd import couple, synth
     torch = torch_gpu
     masks = [synth.workload_windows(4, mask=m) for m in range(8)]
     dW = [[torch.as_tensor(masks[m][s]).cuda() for m in range(8)] for s in range(3)]
     edges = np.arange(0, WIDTH * NBIN + 1, WIDTH)
-    Kb = couple.couple_band_batched(ctx, 0, LCUT, dW[0], None, dW[2], LMAX, spectra=SPEC3, precision="fp32c",
+    Kb = couple.couple_band_batched(ctx, 0, LCUT, dW[0], None, dW[2], LMAX, spectra=SPEC3, precision=precision,
                                     bin_edges=edges)
     for m in range(8):
-        K1 = couple.couple_band(ctx, 0, LCUT, dW[0][m], None, dW[2][m], LMAX, spectra=SPEC3, precision="fp32c",
+        K1 = couple.couple_band(ctx, 0, LCUT, dW[0][m], None, dW[2][m], LMAX, spectra=SPEC3, precision=precision,
                                 bin_edges=edges)
         assert torch.equal(Kb[m], K1), m
     del Kb
     Ku = couple.couple_band_batched(ctx, 0, LCUT, dW[0][:4], None, dW[2][:4], LMAX, spectra=("TT", "EE"),
-                                    precision="fp32c")
+                                    precision=precision)
     for m in (0, 3):
         K1 = couple.couple_band(ctx, 0, LCUT, dW[0][m], None, dW[2][m], LMAX, spectra=("TT", "EE"),
-                                precision="fp32c")
+                                precision=precision)
         assert torch.equal(Ku[m], K1), m
         del K1
