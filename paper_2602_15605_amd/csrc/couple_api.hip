@@ -140,6 +140,12 @@ int check_common(couple_ctx* ctx, const double* W_TT, const double* W_TP, const 
     return COUPLE_OK;
 }
 
+// Xi slots a call's strip launches fill per mask: TT, TE, EE, then EB's (odd L).
+int xi_slots(unsigned spectra) { return (spectra & COUPLE_EB) ? 4 : 3; }
+
+// Whether a call needs the even-L strip (any of TT, TE, EE, BB).
+bool needs_even(unsigned spectra) { return (spectra & (COUPLE_TT | COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0; }
+
 // The even-L strip mode a call's spectra need.
 int strip_mode(unsigned spectra) {
     const bool pol = (spectra & (COUPLE_TE | COUPLE_EE | COUPLE_BB)) != 0;
@@ -371,25 +377,30 @@ int band_one(couple_ctx* ctx, int l3_lo, int l3_hi, const double* W_TT, const do
     return COUPLE_OK;
 }
 
-// Masks per launch of the multi-mask FP32C strip for a batched band call, or 1
-// where it does not apply: it needs FP32C, even L only (no EB), a non-empty
-// band, and room in the Xi workspace for the group's triangles of diagonals
-// 0 .. dmax (three per mask, TT, TE and EE slots).
+// Masks per launch of the multi-mask strips for a batched band call, or 1
+// where they do not apply: they need FP32C or FP64, a non-empty band, room in
+// the Xi workspace for the group's triangles of diagonals 0 .. dmax (three per
+// mask, TT, TE and EE slots, four with EB), and for EB in FP32C the lanes of
+// the one-mask strip (strip_masks_bitwise).
 int masks_per_launch(const couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, int lmax, unsigned spectra,
                      int precision) {
-    if ((precision != COUPLE_FP32C && precision != COUPLE_FP64) || n_masks < 2 || (spectra & COUPLE_EB)) return 1;
+    if ((precision != COUPLE_FP32C && precision != COUPLE_FP64) || n_masks < 2) return 1;
     const int hi = std::min(l3_hi, 2 * lmax);
     if (l3_lo > hi) return 1;
+    if ((spectra & COUPLE_EB) && !couple::strip_masks_bitwise(couple::kStripEB, precision, lmax, hi)) return 1;
     const long long band = couple::diag_offset(lmax, std::min(lmax, hi) + 1);
-    const long long room = 4 * couple::tri_size(ctx->lmax_max) / (3 * band);
-    const int per = couple::strip_masks_per_launch(strip_mode(spectra), precision);
+    const long long room = 4 * couple::tri_size(ctx->lmax_max) / (xi_slots(spectra) * band);
+    int per = couple::kBandMasks;
+    if (needs_even(spectra)) per = std::min(per, couple::strip_masks_per_launch(strip_mode(spectra), precision));
+    if (spectra & COUPLE_EB) per = std::min(per, couple::strip_masks_per_launch(couple::kStripEB, precision));
     return (int)std::min<long long>({(long long)per, room, (long long)n_masks});
 }
 
-// n_masks (<= kBandMasks) masks of a batched band call in one strip launch:
-// their windows are scaled into the context's window sets 0 .. n_masks - 1,
-// the strip writes each mask's Xi triangles (stride: diagonals 0 .. dmax) one
-// after the other, and one bin (or fill) launch serves every mask of the group.
+// n_masks (<= kBandMasks) masks of a batched band call in one strip launch
+// (and one odd-L launch for EB): their windows are scaled into the context's
+// window sets 0 .. n_masks - 1, the strips write each mask's Xi triangles
+// (stride: diagonals 0 .. dmax) one after the other, and one bin (or fill)
+// launch serves every mask of the group.
 int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double* const* W_TT,
                const double* const* W_TP, const double* const* W_PP, int lmax, unsigned spectra, int precision,
                const int* bin_edges, int n_bins, double* out, size_t per_mask, hipStream_t s) {
@@ -397,13 +408,14 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
     const int dmax = std::min(lmax, hi);
     const int n = hi + 1;
     const long long stride = couple::diag_offset(lmax, dmax + 1);
+    const long long mask_stride = xi_slots(spectra) * stride;
     hipError_t e;
     {
         Timed t(ctx, s, 0);
         e = couple::launch_scale_windows_masks(ctx, (spectra & COUPLE_TT) ? W_TT : nullptr,
                                                (spectra & COUPLE_TE) ? W_TP : nullptr,
-                                               (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP : nullptr, n_masks, n,
-                                               nullptr, s);
+                                               (spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB)) ? W_PP : nullptr,
+                                               n_masks, n, nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "scale_windows launch");
     if (precision == COUPLE_FP32C) {
@@ -417,9 +429,14 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
         long long off[couple::kBandMasks];
         for (int m = 0; m < n_masks; ++m) {
             lm[m] = lmax;
-            off[m] = 3 * stride * m;
+            off[m] = mask_stride * m;
         }
-        e = couple::launch_strip_masks(ctx, strip_mode(spectra), precision, n_masks, lm, ctx->xi, off, l3_lo, hi, s);
+        if (needs_even(spectra))
+            e = couple::launch_strip_masks(ctx, strip_mode(spectra), precision, n_masks, lm, ctx->xi, off, l3_lo,
+                                           hi, s);
+        if (e == hipSuccess && (spectra & COUPLE_EB))
+            e = couple::launch_strip_masks(ctx, couple::kStripEB, precision, n_masks, lm, ctx->xi, off, l3_lo, hi,
+                                           s);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
     int src[couple::kMaxOut];
@@ -429,12 +446,12 @@ int band_masks(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, const double*
         // one zero and one bin launch for the group's masks (outputs per_mask apart)
         Timed t(ctx, s, 2);
         e = couple::launch_bin(ctx, lmax, dmax, src, n_out, bin_edges, ctx->edges_dev, n_bins, out, xi, s, ctx->xi,
-                               stride, n_masks, 3 * stride);
+                               stride, n_masks, mask_stride);
     } else {
         // one fill launch for the group's masks
         couple::FillJob jobs[couple::kBandMasks];
         for (int m = 0; m < n_masks; ++m) {
-            jobs[m].xi = ctx->xi + 3 * stride * m;
+            jobs[m].xi = ctx->xi + mask_stride * m;
             jobs[m].xi_stride = stride;
             jobs[m].out = out + m * per_mask;
             jobs[m].lmax = lmax;
@@ -522,9 +539,10 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
 
 namespace {
 
-// Batched FP32C full matrices (even L) through the multi-mask strip: masks in
+// Batched FP32C or FP64 full matrices through the multi-mask strips: masks in
 // order of lmax, descending; groups of strip_masks_per_launch consecutive
-// masks, one strip launch each over the grid of the group's largest lmax (a
+// masks, one strip launch each (two with EB: even and odd L) over the grid of
+// the group's largest lmax (a
 // smaller mask's terms outside its triangle are formed and not stored; its
 // windows are 0 beyond its 2 lmax).  Their Xi stores lie side by side in the
 // batched workspace when it is reserved for all of them, else in the
@@ -533,9 +551,13 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
                  const double* const* W_TP, const double* const* W_PP, unsigned spectra, int precision,
                  double* const* out, hipStream_t s) {
     const int mode = strip_mode(spectra);
-    const int per = couple::strip_masks_per_launch(mode, precision);
+    const bool even = needs_even(spectra), eb = (spectra & COUPLE_EB) != 0;
+    const int slots = xi_slots(spectra);
+    int per = couple::kBandMasks;
+    if (even) per = std::min(per, couple::strip_masks_per_launch(mode, precision));
+    if (eb) per = std::min(per, couple::strip_masks_per_launch(couple::kStripEB, precision));
     long long total = 0;
-    for (int m = 0; m < n_masks; ++m) total += 3 * couple::tri_size(lmax_i[m]);
+    for (int m = 0; m < n_masks; ++m) total += slots * couple::tri_size(lmax_i[m]);
     double* buf = ctx->xi;
     long long cap = 4 * couple::tri_size(ctx->lmax_max);
     if (ctx->bws && (long long)(ctx->bws_bytes / sizeof(double)) >= total && total > cap) {
@@ -555,7 +577,7 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
             int g = std::min({per, n_masks - i, couple::kMaxFillJobs - n_jobs});
             auto need = [&](int k) {
                 long long b = 0;
-                for (int q = 0; q < k; ++q) b += 3 * couple::tri_size(lmax_i[sorted[i + q]]);
+                for (int q = 0; q < k; ++q) b += slots * couple::tri_size(lmax_i[sorted[i + q]]);
                 return b;
             };
             while (g > 0 && used + need(g) > cap) --g;
@@ -563,6 +585,15 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
             while (g > 1 && (lmax_i[sorted[i + g - 1]] > couple::kNarrowLmax) !=
                                 (lmax_i[sorted[i]] > couple::kNarrowLmax))
                 --g;
+            // FP32C's EB rows round from the lane's first row, and the group's grid puts a
+            // mask's rows in lanes as the one-mask grid does only when their lmax agree mod
+            // the rows per lane
+            if (eb && precision == COUPLE_FP32C)
+                for (int q = 1; q < g; ++q)
+                    if ((lmax_i[sorted[i]] - lmax_i[sorted[i + q]]) % couple::kStripR != 0) {
+                        g = q;
+                        break;
+                    }
             if (g == 0) break;
             int lm[couple::kBandMasks], nm[couple::kBandMasks];
             long long off[couple::kBandMasks];
@@ -573,10 +604,10 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
                 lm[k] = lmax_i[m];
                 nm[k] = 2 * lm[k] + 1;
                 off[k] = o;
-                o += 3 * couple::tri_size(lm[k]);
+                o += slots * couple::tri_size(lm[k]);
                 wt[k] = (spectra & COUPLE_TT) ? W_TT[m] : nullptr;
                 wtp[k] = (spectra & COUPLE_TE) ? W_TP[m] : nullptr;
-                wpp[k] = (spectra & (COUPLE_EE | COUPLE_BB)) ? W_PP[m] : nullptr;
+                wpp[k] = (spectra & (COUPLE_EE | COUPLE_BB | COUPLE_EB)) ? W_PP[m] : nullptr;
                 couple::FillJob& j = jobs[n_jobs++];
                 j.xi = buf + off[k];
                 j.xi_stride = couple::tri_size(lm[k]);
@@ -598,7 +629,9 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
             if (e != hipSuccess) return hip_fail(ctx, e, "window_exponents launch");
             {
                 Timed t(ctx, s, 1);
-                e = couple::launch_strip_masks(ctx, mode, precision, g, lm, buf, off, 0, 2 * L, s);
+                if (even) e = couple::launch_strip_masks(ctx, mode, precision, g, lm, buf, off, 0, 2 * L, s);
+                if (e == hipSuccess && eb)
+                    e = couple::launch_strip_masks(ctx, couple::kStripEB, precision, g, lm, buf, off, 0, 2 * L, s);
             }
             if (e != hipSuccess) return hip_fail(ctx, e, "multi-mask strip launch");
             used = o;
@@ -711,7 +744,10 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((precision == COUPLE_FP32C || precision == COUPLE_FP64) && n_masks >= 2 && !(spectra & COUPLE_EB)) {
+    bool masks = (precision == COUPLE_FP32C || precision == COUPLE_FP64) && n_masks >= 2;
+    for (int m = 0; masks && (spectra & COUPLE_EB) && m < n_masks; ++m)
+        masks = couple::strip_masks_bitwise(couple::kStripEB, precision, lmax_i[m], 2 * lmax_i[m]);
+    if (masks) {
         int sorted[couple::kMaxGroups * couple::kMaskGroup];
         int n_sorted = 0;
         for (int gi = 0; gi < p.n_groups; ++gi)

@@ -88,11 +88,15 @@ hipError_t launch_scale_windows_masks(const couple_ctx* ctx, const double* const
 hipError_t launch_window_exponents(const couple_ctx* ctx, int n, hipStream_t s, int n_masks = 1);
 hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision, int l3_lo,
                         int l3_hi, hipStream_t s);
-// Masks one launch_strip_masks call takes in a mode (1: the mode has no such kernel).
+// Masks one launch_strip_masks call takes in a mode.
 int strip_masks_per_launch(int mode, int precision);
+// Whether launch_strip_masks gives a mask of this lmax and l3_hi the bits launch_strip
+// gives it (false only for FP32C's EB when launch_strip would use short lanes).
+bool strip_masks_bitwise(int mode, int precision, int lmax, int l3_hi);
 // FP32C or FP64 over masks 0 .. n_masks - 1 (n_masks <= strip_masks_per_launch) of the window sets,
-// even-L modes, l3 in [l3_lo, l3_hi]: mask m (lmax_m[m]) gets its Xi triangles
-// (TT, TE, EE slots) of diagonals 0 .. min(lmax_m[m], l3_hi) at xi + xi_off[m].
+// l3 in [l3_lo, l3_hi]: mask m (lmax_m[m]) gets its Xi triangles (TT, TE, EE slots for even L,
+// the EB slot 3 for odd L) of diagonals 0 .. min(lmax_m[m], l3_hi) at xi + xi_off[m], each slot
+// min(lmax_m[m], l3_hi) + 1 diagonals long.
 hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, int n_masks, const int* lmax_m,
                               double* xi, const long long* xi_off, int l3_lo, int l3_hi, hipStream_t s);
 

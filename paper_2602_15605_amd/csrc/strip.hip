@@ -727,39 +727,42 @@ strip_fp32c_kernel(StripArgs a, const float* __restrict__ gf, const float* __res
 // float4 slots.  Accumulation per mask, spectrum and row: G-term FMA blocks;
 // with CP > G, CP/G block sums are added plainly into a mid sum; every CP steps
 // (and at a chunk's end) a Kahan step in float32; the pair is combined,
-// rescaled and unscaled in float64.  Even L only.
+// rescaled and unscaled in float64.  The odd-L mode (EB) shares P and the
+// exact f1 f3^2 factor of strip_fp32c_kernel's EB mode the same way.
 template <int MODE, int M, int G, int CP>
 __global__ void __launch_bounds__(kWave)
 strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float* __restrict__ hf) {
     constexpr int R = kStripR;
     constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
     constexpr bool TE = MODE == kModePol;
-    constexpr bool TTS = MODE != kModeEE;
+    constexpr bool TTS = MODE != kModeEE;               // the first sum (TT, or EB's)
+    constexpr bool EB = MODE == kModeEB;
     constexpr bool MID = CP > G;
     constexpr int KC = kStripChunkF32;
     using W = Win<R, KC>;
     constexpr int B = W::kB;
     constexpr int RB = kStripRebase;
-    static_assert(MODE != kModeEB, "even L only");
     static_assert(M >= 1 && M <= 4, "one float4 lane per mask");
     static_assert(KC % RB == 0 && RB % G == 0 && G % R == 0 && CP % G == 0 && KC % CP == 0,
                   "chunk must hold whole splits, blocks and Kahan periods");
     __shared__ float s_g[W::kPhys];
     __shared__ float s_h[W::kPhys];
     // a step's U packed into NV float4: slots x[m] = m, y[m] = NX + m, z[m] = NX + NY + m,
-    // then D (N' expansion) in slot NU when that fits the last float4, else in s_uw
+    // then D (N' expansion, or EB's c - c_s) in slot NU when that fits the last float4, else in s_uw
+    constexpr bool DW = POL || EB;
     constexpr int NX = TTS ? M : 0, NY = TE ? M : 0, NZ = POL ? M : 0;
     constexpr int NU = NX + NY + NZ;
-    constexpr bool WPACK = POL && NU % 4 != 0;
+    constexpr bool WPACK = DW && NU % 4 != 0;
     constexpr int NV = (NU + (WPACK ? 1 : 0) + 3) / 4;
     __shared__ float4 s_u4[KC][NV];
-    __shared__ float s_uw[(POL && !WPACK) ? KC : 1];
+    __shared__ float s_uw[(DW && !WPACK) ? KC : 1];
 
     int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
     if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
+    const int de = EB ? d + 1 : d;                       // l3 = de + 2k
     const int blk_max = A + B - 1;
-    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
-    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+    const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
 
@@ -770,27 +773,44 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
     // c_s, exact, carried from split to split (strip_fp32c_kernel)
     int tq[R];
     long long q64[R];
+    // EB: gam = sig(sig+1), mu, and the exact offsets of rows j from the lane's first row
+    int gam[R], mu[R];
+    float dg[R], dm[R];
     int c_cur;
     {
-        const int l3s = d + 2 * k_lo;
+        const int l3s = de + 2 * k_lo;
         c_cur = l3s * (l3s + 1);
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         qf[j] = rf[j] = 0.0f;
         const long long l1 = l1_0 + j, l2 = l1 + d;
-        const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
-        const long long t = (long long)c_cur - (aa + bb - 1);
-        tq[j] = (int)t;
-        q64[j] = t * t - (2 * aa * bb + 1);
+        if (EB) {
+            const long long sg = l1 + l2 + 1, tau = sg + 1;
+            gam[j] = (int)(sg * (sg + 1));
+            mu[j] = (int)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
+            tq[j] = 0;
+            q64[j] = 0;
+        } else {
+            const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
+            const long long t = (long long)c_cur - (aa + bb - 1);
+            gam[j] = mu[j] = 0;
+            tq[j] = (int)t;
+            q64[j] = t * t - (2 * aa * bb + 1);
+        }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             kt[j][m] = kte[j][m] = kee[j][m] = ct[j][m] = cte[j][m] = cee[j][m] = 0.0f;
             mt[j][m] = mte[j][m] = mee[j][m] = 0.0f;
         }
     }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        dg[j] = (float)(gam[j] - gam[0]);
+        dm[j] = (float)(mu[j] - mu[0]);
+    }
     // per-mask power-of-two scales at the item's first l3 (strip_fp32c_kernel)
-    const int l3f = min(d + 2 * k_lo, a.l3_hi);
+    const int l3f = min(de + 2 * k_lo, a.l3_hi);
     int ex_tt[M], ex_tp[M], ex_pp[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -806,7 +826,7 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
         const int kc_r = (kc + G - 1) / G * G;           // staged U of steps kc .. kc_r - 1 is 0
         __syncthreads();
         const int g_base = A - k0 - KC + 1;
-        const int h_base = A + d + k0;
+        const int h_base = A + de + k0;
         const int g_off = KC - kc_r;
         for (int i = lane; i < B + kc_r - 1; i += kWave) {
             const int eg = g_base + g_off + i, eh = h_base + i;
@@ -820,24 +840,29 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
             float uw = 0.0f;
             if (st < kc) {
                 const int k = k0 + st;
-                const int l3 = d + 2 * k;
-                const int l3c = d + 2 * (k0 + st / RB * RB);    // l3 at this step's split
-                const double gg = a.g[k] * a.g[d + k];
+                const int l3 = de + 2 * k;
+                const int l3c = de + 2 * (k0 + st / RB * RB);   // l3 at this step's split
+                const double gg = a.g[k] * a.g[de + k];
+                const long long c = (long long)l3 * (l3 + 1);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     if (m >= a.n_masks) continue;
                     const double* w = a.wp + (long long)m * a.wp_mask_stride;
-                    if (TTS) uf[m] = (float)ldexp(w[l3] * gg, -ex_tt[m]);
+                    if (EB)
+                        uf[m] = (float)(ldexp(w[2 * a.wp_stride + l3] * gg, -ex_pp[m]) *
+                                        (double)(c - (long long)d * (d + 1)));
+                    else if (TTS)
+                        uf[m] = (float)ldexp(w[l3] * gg, -ex_tt[m]);
                     if (TE) uf[NX + m] = (float)ldexp(w[a.wp_stride + l3] * gg, -ex_tp[m]);
                     if (POL) uf[NX + NY + m] = (float)ldexp(w[2 * a.wp_stride + l3] * gg, -ex_pp[m]);
                 }
-                if (POL) uw = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
+                if (DW) uw = (float)(l3 * (l3 + 1) - l3c * (l3c + 1));
             }
             if (WPACK) uf[NU] = uw;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 s_u4[st][v] = make_float4(uf[4 * v], uf[4 * v + 1], uf[4 * v + 2], uf[4 * v + 3]);
-            if (POL && !WPACK) s_uw[st] = uw;
+            if (DW && !WPACK) s_uw[st] = uw;
         }
         __syncthreads();
 
@@ -851,7 +876,20 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
         }
         const float* pg = s_g + (R + 1) * (lane + KC / R - 1) + (R - 1);
         const float* ph = s_h + (R + 1) * lane + (R - 1);
+        float thi = 0.0f, tlo = 0.0f, t3hi = 0.0f, t3lo = 0.0f;   // EB: first row's split
         for (int sb = 0; sb < kc_r; sb += G) {
+            if (EB && sb % RB == 0) {
+                // f1 = sig(sig+1) - c = T - D(k), T = sig(sig+1) - c_s, and
+                // f3 = c + mu = T3 + D(k), T3 = c_s + mu, each split exactly into hi + lo
+                const int l3c = de + 2 * (k0 + sb);
+                const int cc = l3c * (l3c + 1);
+                const int T = gam[0] - cc;
+                thi = (float)T;
+                tlo = (float)(T - (int)thi);
+                const int T3 = cc + mu[0];
+                t3hi = (float)T3;
+                t3lo = (float)(T3 - (int)t3hi);
+            }
             if (POL && sb % RB == 0) {
                 // move (T, Q) to this split's c_s: Q(c + D) = Q + D T + D (T + D)
                 const int l3c = d + 2 * (k0 + sb);
@@ -892,13 +930,23 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
                         uf[4 * v + 2] = q4.z;
                         uf[4 * v + 3] = q4.w;
                     }
-                    const float w = !POL ? 0.0f : WPACK ? uf[WPACK ? NU : 0] : s_uw[s0 + u];
+                    const float w = !DW ? 0.0f : WPACK ? uf[WPACK ? NU : 0] : s_uw[s0 + u];
                     const float* xs = uf;
                     const float* ys = uf + NX;
                     const float* zs = uf + NX + NY;
+                    // EB: first row exact split; rows j > 0 add their exact integer offsets
+                    const float f10 = thi + (tlo - w), f30 = t3hi + (w + t3lo);
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
                         const float P = gw[j] * hw[j];
+                        if (EB) {
+                            const float f1 = j == 0 ? f10 : f10 + dg[j];
+                            const float f3 = j == 0 ? f30 : f30 + dm[j];
+                            const float e = P * ((f1 * f3) * f3);
+#pragma unroll
+                            for (int m = 0; m < M; ++m) bt[j][m] = __builtin_fmaf(xs[m], e, bt[j][m]);
+                            continue;
+                        }
                         if (TTS)
 #pragma unroll
                             for (int m = 0; m < M; ++m) bt[j][m] = __builtin_fmaf(xs[m], P, bt[j][m]);
@@ -969,7 +1017,11 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
         for (int j = 0; j < R; ++j) {
             const int l1 = l1_0 + j;
             if (l1 < 0 || l1 >= rows) continue;
-            const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            const double sc = (POL || EB) ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            if (EB) {
+                xm[3 * st + l1] = ldexp((sc * sc) * ((double)kt[j][m] - (double)ct[j][m]), ex_pp[m]);
+                continue;
+            }
             if (TTS) xm[l1] = ldexp((double)kt[j][m] - (double)ct[j][m], ex_tt[m]);
             if (TE) xm[st + l1] = ldexp(sc * ((double)kte[j][m] - (double)cte[j][m]), ex_tp[m]);
             if (POL) xm[2 * st + l1] = ldexp((sc * sc) * ((double)kee[j][m] - (double)cee[j][m]), ex_pp[m]);
@@ -983,7 +1035,8 @@ strip_fp32c_masks_kernel(StripArgs a, const float* __restrict__ gf, const float*
 // and spectrum).  Each mask's U and sums are those of strip_fp64_kernel: a
 // plain FMA chain per row in step order, so the chunk length (kStripChunkF64Masks
 // steps, short enough for the masks' float64 U to leave LDS for two waves per
-// SIMD) does not change a result bit.  Even L only.
+// SIMD) does not change a result bit.  The odd-L mode (EB) forms
+// strip_fp64_kernel's exact f1 f3^2 factor once per term for all masks.
 
 template <int MODE, int M, bool WIDE>
 __global__ void __launch_bounds__(kWave)
@@ -991,16 +1044,16 @@ strip_fp64_masks_kernel(StripArgs a) {
     constexpr int R = kStripR;
     constexpr bool POL = MODE == kModePol || MODE == kModePolEE || MODE == kModeEE;
     constexpr bool TE = MODE == kModePol;
-    constexpr bool TTS = MODE != kModeEE;
+    constexpr bool TTS = MODE != kModeEE;               // the first sum (TT, or EB's)
+    constexpr bool EB = MODE == kModeEB;
     constexpr int KC = kStripChunkF64Masks;
     using W = Win<R, KC>;
     constexpr int B = W::kB;
-    static_assert(MODE != kModeEB, "even L only");
     static_assert(M >= 1 && M <= kBandMasks, "masks per launch");
     static_assert(KC % R == 0 && KC % kWave == 0, "chunk of whole step groups and lanes");
     // a step's U in NV double2: slots x[m] = m, y[m] = NX + m, z[m] = NX + NY + m, then c
     constexpr int NX = TTS ? M : 0, NY = TE ? M : 0, NZ = POL ? M : 0;
-    constexpr int NU = NX + NY + NZ + (POL ? 1 : 0);
+    constexpr int NU = NX + NY + NZ + ((POL || EB) ? 1 : 0);
     constexpr int NV = (NU + 1) / 2;
     __shared__ double s_g[W::kPhys];
     __shared__ double s_h[W::kPhys];
@@ -1008,13 +1061,15 @@ strip_fp64_masks_kernel(StripArgs a) {
 
     int d, A;                                            // l2 = l1 + d; rows A .. A + B - 1
     if (!strip_item<B>(a, blockIdx.x, &d, &A)) return;
+    const int de = EB ? d + 1 : d;                       // l3 = de + 2k
     const int blk_max = A + B - 1;
-    const int k_lo = max(0, (a.l3_lo - d + 1) >> 1);
-    const int k_hi = min(blk_max, (a.l3_hi - d) >> 1);
+    const int k_lo = max(0, (a.l3_lo - de + 1) >> 1);
+    const int k_hi = min(blk_max, (a.l3_hi - de) >> 1);
     const int lane = threadIdx.x;
     const int l1_0 = A + R * lane;
 
-    // N' per row as in strip_fp64_kernel (narrow: c (c - gam2) + kap; WIDE: t^2 - kap - blo)
+    // N' per row as in strip_fp64_kernel (narrow: c (c - gam2) + kap; WIDE: t^2 - kap - blo);
+    // EB: gam2 = sig(sig+1), kap = mu
     double tt[R][M], te[R][M], ee[R][M], gam2[R], kap[R], blo[R], gw[R], hw[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -1023,7 +1078,11 @@ strip_fp64_masks_kernel(StripArgs a) {
         blo[j] = 0.0;
         const long long l1 = l1_0 + j, l2 = l1 + d;
         const long long aa = l1 * (l1 + 1), bb = l2 * (l2 + 1);
-        if (WIDE) {
+        if (EB) {
+            const long long sg = l1 + l2 + 1, tau = sg + 1;
+            gam2[j] = (double)(sg * (sg + 1));
+            kap[j] = (double)(2 * (l1 + 2) * (l2 + 2) - tau * (tau + 1));
+        } else if (WIDE) {
             const long long beta = 2 * aa * bb + 1;
             gam2[j] = (double)(aa + bb - 1);
             kap[j] = (double)beta;
@@ -1039,7 +1098,7 @@ strip_fp64_masks_kernel(StripArgs a) {
         const int kc_r = (kc + R - 1) / R * R;           // staged U of steps kc .. kc_r - 1 is 0
         __syncthreads();
         const int g_base = A - k0 - KC + 1;
-        const int h_base = A + d + k0;
+        const int h_base = A + de + k0;
         const int g_off = KC - kc_r, n_win = B + kc_r - 1;
         for (int i = lane; i < n_win; i += kWave) {
             const int eg = g_base + g_off + i, eh = h_base + i;
@@ -1052,17 +1111,21 @@ strip_fp64_masks_kernel(StripArgs a) {
             for (int i = 0; i < 2 * NV; ++i) uf[i] = 0.0;
             if (st < kc) {
                 const int k = k0 + st;
-                const int l3 = d + 2 * k;
-                const double gg = a.g[k] * a.g[d + k];
+                const int l3 = de + 2 * k;
+                const double gg = a.g[k] * a.g[de + k];
+                const long long c = (long long)l3 * (l3 + 1);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     if (m >= a.n_masks) continue;
                     const double* w = a.wp + (long long)m * a.wp_mask_stride;
-                    if (TTS) uf[m] = w[l3] * gg;
+                    if (EB)
+                        uf[m] = w[2 * a.wp_stride + l3] * gg * (double)(c - (long long)d * (d + 1));
+                    else if (TTS)
+                        uf[m] = w[l3] * gg;
                     if (TE) uf[NX + m] = w[a.wp_stride + l3] * gg;
                     if (POL) uf[NX + NY + m] = w[2 * a.wp_stride + l3] * gg;
                 }
-                if (POL) uf[NU - 1] = (double)((long long)l3 * (l3 + 1));
+                if (POL || EB) uf[NU - 1] = (double)c;
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) s_u2[st][v] = make_double2(uf[2 * v], uf[2 * v + 1]);
@@ -1095,10 +1158,19 @@ strip_fp64_masks_kernel(StripArgs a) {
                     uf[2 * v] = q2.x;
                     uf[2 * v + 1] = q2.y;
                 }
-                const double c = POL ? uf[POL ? NU - 1 : 0] : 0.0;
+                const double c = (POL || EB) ? uf[(POL || EB) ? NU - 1 : 0] : 0.0;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const double P = gw[j] * hw[j];
+                    if (EB) {
+                        // (sig(sig+1) - c) (c + mu)^2, each factor an exact integer
+                        const double f1 = gam2[j] - c;
+                        const double f3 = c + kap[j];
+                        const double e = P * ((f1 * f3) * f3);
+#pragma unroll
+                        for (int m = 0; m < M; ++m) tt[j][m] = __builtin_fma(uf[m], e, tt[j][m]);
+                        continue;
+                    }
                     if (TTS)
 #pragma unroll
                         for (int m = 0; m < M; ++m) tt[j][m] = __builtin_fma(uf[m], P, tt[j][m]);
@@ -1134,7 +1206,11 @@ strip_fp64_masks_kernel(StripArgs a) {
         for (int j = 0; j < R; ++j) {
             const int l1 = l1_0 + j;
             if (l1 < 0 || l1 >= rows) continue;
-            const double sc = POL ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            const double sc = (POL || EB) ? 0.5 * a.cl[l1] * a.cl[l1 + d] : 0.0;
+            if (EB) {
+                xm[3 * st + l1] = (sc * sc) * tt[j][m];
+                continue;
+            }
             if (TTS) xm[l1] = tt[j][m];
             if (TE) xm[st + l1] = sc * te[j][m];
             if (POL) xm[2 * st + l1] = (sc * sc) * ee[j][m];
@@ -1274,9 +1350,17 @@ hipError_t launch_strip(const couple_ctx* ctx, int lmax, int mode, int precision
 }
 
 int strip_masks_per_launch(int mode, int precision) {
-    if (mode == kStripEB) return 1;
     if (precision == COUPLE_FP64) return mode == kStripPolEE ? kMasksPolEEF64 : mode == kStripPol ? kMasksPolF64 : kBandMasks;
     return mode == kStripPolEE ? kMasksPolEE : mode == kStripPol ? kMasksPol : kBandMasks;
+}
+
+bool strip_masks_bitwise(int mode, int precision, int lmax, int l3_hi) {
+    // FP32C's EB rows round f1 and f3 from the lane's first row: a lane must hold the
+    // same rows as in launch_strip, which drops to kStripRSmall rows per lane on
+    // small item counts
+    if (mode != kStripEB || precision != COUPLE_FP32C) return true;
+    const int dmax = std::min(lmax, l3_hi);
+    return count_items(lmax, dmax, kWave * kStripR, dmax < lmax) >= kStripSmallItemsF32;
 }
 
 hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, int n_masks, const int* lmax_m,
@@ -1331,6 +1415,8 @@ hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, in
             hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeEE, kBandMasks, true>), grid, block, 0, s, a);
         else if (mode == kStripEE)
             hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeEE, kBandMasks, false>), grid, block, 0, s, a);
+        else if (mode == kStripEB)
+            hipLaunchKernelGGL((strip_fp64_masks_kernel<kModeEB, kBandMasks, false>), grid, block, 0, s, a);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
@@ -1344,6 +1430,8 @@ hipError_t launch_strip_masks(const couple_ctx* ctx, int mode, int precision, in
         hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModeTT, kBandMasks, G, CP>), grid, block, 0, s, a, gf, hf);
     else if (mode == kStripEE)
         hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModeEE, kBandMasks, G, CP>), grid, block, 0, s, a, gf, hf);
+    else if (mode == kStripEB)
+        hipLaunchKernelGGL((strip_fp32c_masks_kernel<kModeEB, kBandMasks, G, CP>), grid, block, 0, s, a, gf, hf);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -101,8 +101,10 @@ def test_band_unbinned_full_size_fp64(torch_gpu, ctx, oracle_bulk, spectra):
 def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
     """A batched call gives, mask by mask, what single calls give (bitwise),
     binned and not, K or Xi, for 1 .. 9 masks.  The batched call runs the
-    multi-mask strip (four masks per launch, fewer with TE; EB keeps one launch
-    per mask), whose per-mask arithmetic is that of the single-mask kernels."""
+    multi-mask strips (four masks per launch, fewer with TE; EB in FP64 in a
+    launch of its own), whose per-mask arithmetic is that of the single-mask
+    kernels.  FP32C's EB stays one mask per launch at this size: the one-mask
+    strip runs short lanes there."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
     lmax, lo, hi = 700, 3, 250
@@ -121,6 +123,31 @@ def test_band_batched_equals_single(torch_gpu, ctx, precision, spectra):
                                             bin_edges=edges, xi=xi)
             for m in range(n):
                 assert torch.equal(Kb[m], singles[(edges is None, m)]), (n, m, edges is None)
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+@pytest.mark.parametrize("spectra", [("EE", "BB", "EB"), ("TT", "TE", "EB"), ("EB",)])
+def test_band_batched_eb_multimask_equal_single(torch_gpu, ctx, precision, spectra):
+    """EB through the multi-mask odd-L strip at a size where the one-mask FP32C
+    strip runs full lanes (at least 8192 work items: lmax 6000 with l3 <= 400,
+    lmax 3000 with l3 <= 700): 1 .. 5 masks binned at lmax 6000, 2 unbinned at
+    lmax 3000, equal to single calls bitwise."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    rng = np.random.default_rng(91)
+    for lmax, lo, hi, edges, counts in ((6000, 1, 400, list(range(0, 6001, 60)) + [6001], (1, 2, 4, 5)),
+                                        (3000, 0, 700, None, (2,))):
+        Ws = [[torch.as_tensor(rng.uniform(0.1, 1.0, 2 * lmax + 1)).cuda() for _ in range(3)] for _ in range(5)]
+        singles = [couple.couple_band(ctx, lo, hi, *Ws[m], lmax, spectra=spectra, precision=precision,
+                                      bin_edges=edges) for m in range(max(counts))]
+        for n in counts:
+            Kb = couple.couple_band_batched(ctx, lo, hi, [w[0] for w in Ws[:n]], [w[1] for w in Ws[:n]],
+                                            [w[2] for w in Ws[:n]], lmax, spectra=spectra, precision=precision,
+                                            bin_edges=edges)
+            for m in range(n):
+                assert torch.equal(Kb[m], singles[m]), (lmax, n, m)
+            del Kb
+        del singles
 
 
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])

@@ -104,7 +104,8 @@ def test_batched_workload3_sampled_rows(torch_gpu, ctx, oracle_bulk, precision, 
                                      ("TT", "TE", "EE", "BB", "EB")])
 def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision, spectra):
     """couple_matrix_batched in FP64 and FP32C equals couple_matrix mask by mask,
-    bitwise.  Without EB it runs the multi-mask strip: masks sorted by lmax,
+    bitwise.  It runs the multi-mask strips (FP32C's EB only where every mask's
+    one-mask strip runs full lanes, not at these sizes): masks sorted by lmax,
     four per launch (with TE three in FP32C, two in FP64), over the grid of the
     group's largest lmax, so a smaller mask's rows run in other blocks and past
     their own end; their sums still come out bitwise equal (extra all-zero
@@ -119,6 +120,27 @@ def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision, spect
     for m in range(len(lmaxes)):
         K1 = couple.couple_matrix(ctx, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=spectra, precision=precision)
         assert torch.equal(outs[m], K1), (m, lmaxes[m])
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_batched_eb_multimask_equal_single_calls(torch_gpu, ctx, precision):
+    """Full matrices with EB through the multi-mask odd-L strip: four masks of
+    lmax 2100 .. 2254 (large enough for the one-mask FP32C strip's full lanes;
+    FP32C groups masks whose lmax agree mod 4, here {2254, 2250} and {2180, 2100},
+    FP64 all four), even and odd strips per group, equal to couple_matrix bitwise."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [2100, 2250, 2180, 2254]
+    Ws = _rand_windows(lmaxes, 12)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    for spectra in (("TT", "EE", "BB", "EB"), ("EB",)):
+        outs = couple.couple_matrix_batched(ctx, lmaxes, dW[0], dW[1], dW[2], spectra=spectra, precision=precision)
+        for m in range(len(lmaxes)):
+            K1 = couple.couple_matrix(ctx, dW[0][m], dW[1][m], dW[2][m], lmaxes[m], spectra=spectra,
+                                      precision=precision)
+            assert torch.equal(outs[m], K1), (spectra, m, lmaxes[m])
+            del K1
+        del outs
 
 
 def test_batched_fp32c_xi_workspace_waves(torch_gpu, oracle_bulk):
