@@ -166,15 +166,17 @@ int couple_band(couple_ctx *ctx, int l3_lo, int l3_hi, const double *W_TT, const
                 const int *bin_edges, int n_bins, double *out, void *stream);
 
 /*
- * couple_band_batched -- couple_band for n_masks windows in one call.  Without
- * EB, up to four masks (three in FP32C, two in FP64 when TE is asked for)
- * share one strip launch: the
- * g/h factors and the (-2 2 0) polynomial of each term are formed once for
- * them, and each mask's sums are those of couple_band (the results are
- * bitwise equal, in COUPLE_FP64 and COUPLE_FP32C).  Such a group needs its Xi
- * triangles of diagonals 0 .. min(lmax, l3_hi) in the context's workspace, 3
- * per mask; the group is cut to what fits, and where a single mask is left the
- * per-mask launches run.  With EB: per-mask work back to back on `stream`.
+ * couple_band_batched -- couple_band for n_masks windows in one call.  Up to
+ * four masks (three in FP32C, two in FP64 when TE is asked for) share one
+ * strip launch, and with EB one odd-L launch as well: the g/h factors and the
+ * (-2 2 0) polynomial of each term are formed once for them, and each mask's
+ * sums are those of couple_band (the results are bitwise equal, in
+ * COUPLE_FP64 and COUPLE_FP32C).  Such a group needs its Xi triangles of
+ * diagonals 0 .. min(lmax, l3_hi) in the context's workspace, 3 per mask (4
+ * with EB); the group is cut to what fits, and where a single mask is left the
+ * per-mask launches run, as they do for FP32C with EB when the band has fewer
+ * than 8192 strip items of 256 rows (couple_band's strip then runs 128-row
+ * items, whose EB sums round differently).
  *   W_TT, W_TP, W_PP : HOST arrays of n_masks DEVICE pointers (an array may
  *                      be NULL when no requested spectrum uses it).
  *   out              : device float64, n_masks consecutive outputs of the
@@ -221,17 +223,20 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *                     couple_reserve_batched first.  No allocation, no host
  *                     synchronisation: the call can be captured in a graph.
  *                     COUPLE_FP64 / COUPLE_FP32C -- each mask's result is
- *                     couple_matrix's, bitwise.  Without EB, masks sorted by
+ *                     couple_matrix's, bitwise.  Masks sorted by
  *                     lmax run in groups of four (with TE three in FP32C,
- *                     two in FP64) through one
- *                     strip launch each, over the grid of the group's
+ *                     two in FP64) through one strip launch each (and one
+ *                     odd-L launch with EB), over the grid of the group's
  *                     largest lmax, sharing each term's g/h factors and
  *                     (-2 2 0) polynomial; their Xi stores go to the batched
  *                     workspace when couple_reserve_batched sized it for the
  *                     batch, else to the context's (in turns of what fits),
- *                     and one fill launch follows per turn.  With EB:
- *                     couple_matrix per mask.  Kernels only, no allocation
- *                     or host synchronisation: capturable in a graph.
+ *                     and one fill launch follows per turn.  FP32C with EB
+ *                     groups only masks whose lmax agree mod 4, and runs
+ *                     couple_matrix per mask when any lmax is below 1792
+ *                     (where couple_matrix's strip runs 128-row items).
+ *                     Kernels only, no allocation or host synchronisation:
+ *                     capturable in a graph.
  * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),
  * EDEVICE.
  */

@@ -233,9 +233,9 @@ def couple_band_batched(ctx, l3_lo, l3_hi, W_TT, W_TP, W_PP, lmax, spectra=("TT"
                         precision="fp64", bin_edges=None, out=None, stream=None, xi=False):
     """couple_band for a list of masks: ``W_*`` are lists of GPU tensors (or None).
 
-    Returns [n_masks, n_spec, ...] with the couple_band layout per mask.  Without
-    EB the masks share strip launches (up to four per launch); every mask's
-    result is bitwise that of couple_band.
+    Returns [n_masks, n_spec, ...] with the couple_band layout per mask.  The
+    masks share strip launches (up to four per launch; EB in an odd-L launch
+    of its own); every mask's result is bitwise that of couple_band.
     """
     import torch
     bits = _spectra_bits(spectra, xi)
