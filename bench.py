@@ -308,7 +308,7 @@ def run_extras(torch, couple, synth, args):
             "flop_per_triple_single_mask": FLOP_PER_TRIPLE_BAND,
             "strip_single_mask_equiv_tflops": tflops, "strip_single_mask_equiv_frac": tflops / peak,
             "note": ("two multi-mask strip launches of four masks (windows once per group), then one zero and "
-                     "one bin launch per mask; strip_tflops / strip_roofline_frac count the FLOP executed "
+                     "one bin launch per group; strip_tflops / strip_roofline_frac count the FLOP executed "
                      "(P, N' and the two products once per term for the group, 2 FMAs per mask); "
                      "strip_single_mask_equiv_* charge every mask the single-mask 10 FLOP per triple, "
                      "the rate one launch per mask would need to match")}
@@ -319,6 +319,24 @@ def run_extras(torch, couple, synth, args):
                                                           bin_edges=edges, out=res, xi=True), steps, warm)
     out["band_lmax10000_cut1000_8masks_binned_xi_fp32c"] = {
         "ms_per_call": ms, "masks": 8, "spectra": ["TT", "EE", "BB"], "bins": 200, "output": "Xi"}
+    # with the odd-L EB matrix: the multi-mask odd-L strip runs beside the even one; timed
+    # against eight one-mask calls (the results are bitwise equal)
+    pol = ("EE", "BB", "EB")
+    res_pol = torch.empty((8, 3, 200, 200), dtype=torch.float64, device="cuda")
+    for prec in ("fp32c", "fp64"):
+        ms = _timed(torch, lambda: couple.couple_band_batched(ctx, 0, cut, None, None, dW[2], L, spectra=pol,
+                                                              precision=prec, bin_edges=edges, out=res_pol),
+                    steps, warm)
+
+        def one_mask_calls():
+            for m in range(8):
+                couple.couple_band(ctx, 0, cut, None, None, dW[2][m], L, spectra=pol, precision=prec,
+                                   bin_edges=edges, out=res_pol[m])
+
+        ms_one = _timed(torch, one_mask_calls, steps, warm)
+        out["band_lmax10000_cut1000_8masks_binned_eebbeb_" + prec] = {
+            "ms_per_call": ms, "one_mask_calls_ms": ms_one, "masks": 8, "spectra": list(pol), "bins": 200}
+    del res_pol
     couple.couple_free(ctx)
     del dW, res
     # batched: 32 masks, lmax uniform in [500, 4000], 4 spectra, matrix-core contraction
