@@ -262,6 +262,45 @@ def test_batched_graph_replay(torch_gpu, ctx, precision):
         del x
 
 
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_batched_eb_graph_replay(torch_gpu, ctx, precision):
+    """With EB the batched FP32C / FP64 call (even and odd-L multi-mask strips,
+    lmax 1804 .. 2000, equal mod 4) captures into a graph that replays to the
+    eager result, replay after replay, with eager work in between."""
+    from paper_2602_15605_amd import couple
+    torch = torch_gpu
+    lmaxes = [1900, 2000, 1804]
+    spectra = ("TT", "EE", "BB", "EB")
+    Ws = _rand_windows(lmaxes, 44)
+    dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
+    eager = [o.clone() for o in couple.couple_matrix_batched(ctx, lmaxes, dW[0], None, dW[2], spectra=spectra,
+                                                            precision=precision)]
+    outs = [torch.empty_like(o) for o in eager]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], None, dW[2], spectra=spectra, precision=precision,
+                                     outs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        couple.couple_matrix_batched(ctx, lmaxes, dW[0], None, dW[2], spectra=spectra, precision=precision,
+                                     outs=outs)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        x = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")  # eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for m in range(len(lmaxes)):
+            assert torch.equal(outs[m], eager[m]), (rep, m)
+        del x
+    K1 = couple.couple_matrix(ctx, dW[0][1], None, dW[2][1], lmaxes[1], spectra=spectra, precision=precision)
+    assert torch.equal(outs[1], K1)
+    del graph, outs, eager, K1
+
+
 @pytest.mark.parametrize("precision,tol", MFMA)
 def test_batched_64_masks_four_groups(torch_gpu, ctx, oracle_bulk, precision, tol):
     """The largest batch: 64 masks in four column groups (64 fill jobs), with
