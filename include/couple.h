@@ -233,8 +233,8 @@ int couple_reserve_batched(couple_ctx *ctx, int n_masks, const int *lmax_i);
  *                     batch, else to the context's (in turns of what fits),
  *                     and one fill launch follows per turn.  FP32C with EB
  *                     groups only masks whose lmax agree mod 4, and runs
- *                     couple_matrix per mask when any lmax is below 1792
- *                     (where couple_matrix's strip runs 128-row items).
+ *                     masks of lmax below 1792 (where couple_matrix's strip
+ *                     runs 128-row items) through couple_matrix one by one.
  *                     Kernels only, no allocation or host synchronisation:
  *                     capturable in a graph.
  * Errors: EINVAL (as couple_matrix, naming the mask; workspace too small),

@@ -539,12 +539,12 @@ int couple_band_batched(couple_ctx* ctx, int n_masks, int l3_lo, int l3_hi, cons
 
 namespace {
 
-// Batched FP32C or FP64 full matrices through the multi-mask strips: masks in
-// order of lmax, descending; groups of strip_masks_per_launch consecutive
-// masks, one strip launch each (two with EB: even and odd L) over the grid of
-// the group's largest lmax (a
-// smaller mask's terms outside its triangle are formed and not stored; its
-// windows are 0 beyond its 2 lmax).  Their Xi stores lie side by side in the
+// Batched FP32C or FP64 full matrices through the multi-mask strips: masks
+// sorted[0 .. n_masks - 1] (indices into lmax_i, W_*, out), in order of lmax,
+// descending; groups of strip_masks_per_launch consecutive masks, one strip
+// launch each (two with EB: even and odd L) over the grid of the group's
+// largest lmax (a smaller mask's terms outside its triangle are formed and not
+// stored; its windows are 0 beyond its 2 lmax).  Their Xi stores lie side by side in the
 // batched workspace when it is reserved for all of them, else in the
 // context's Xi workspace; one fill launch follows for the masks it holds.
 int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lmax_i, const double* const* W_TT,
@@ -557,7 +557,7 @@ int matrix_masks(couple_ctx* ctx, int n_masks, const int* sorted, const int* lma
     if (even) per = std::min(per, couple::strip_masks_per_launch(mode, precision));
     if (eb) per = std::min(per, couple::strip_masks_per_launch(couple::kStripEB, precision));
     long long total = 0;
-    for (int m = 0; m < n_masks; ++m) total += slots * couple::tri_size(lmax_i[m]);
+    for (int i = 0; i < n_masks; ++i) total += slots * couple::tri_size(lmax_i[sorted[i]]);
     double* buf = ctx->xi;
     long long cap = 4 * couple::tri_size(ctx->lmax_max);
     if (ctx->bws && (long long)(ctx->bws_bytes / sizeof(double)) >= total && total > cap) {
@@ -744,19 +744,30 @@ int couple_matrix_batched(couple_ctx* ctx, int n_masks, const int* lmax_i, const
         }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    bool masks = (precision == COUPLE_FP32C || precision == COUPLE_FP64) && n_masks >= 2;
-    for (int m = 0; masks && (spectra & COUPLE_EB) && m < n_masks; ++m)
-        masks = couple::strip_masks_bitwise(couple::kStripEB, precision, lmax_i[m], 2 * lmax_i[m]);
-    if (masks) {
-        int sorted[couple::kMaxGroups * couple::kMaskGroup];
-        int n_sorted = 0;
-        for (int gi = 0; gi < p.n_groups; ++gi)
-            for (int m = 0; m < p.n_masks[gi]; ++m) sorted[n_sorted++] = order[gi * couple::kMaskGroup + m];
-        return matrix_masks(ctx, n_masks, sorted, lmax_i, W_TT, W_TP, W_PP, spectra, precision, out, s);
+    int sorted[couple::kMaxGroups * couple::kMaskGroup];
+    int n_sorted = 0;
+    for (int gi = 0; gi < p.n_groups; ++gi)
+        for (int m = 0; m < p.n_masks[gi]; ++m) sorted[n_sorted++] = order[gi * couple::kMaskGroup + m];
+    // masks (sorted by lmax, descending) through the multi-mask strips: all of them, but with
+    // EB only those whose one-mask strip gets the same bits (strip_masks_bitwise holds from
+    // some lmax up); the rest run couple_matrix one by one
+    int n_multi = 0;
+    if ((precision == COUPLE_FP32C || precision == COUPLE_FP64) && n_masks >= 2) {
+        n_multi = n_masks;
+        if (spectra & COUPLE_EB)
+            while (n_multi > 0 && !couple::strip_masks_bitwise(couple::kStripEB, precision, lmax_i[sorted[n_multi - 1]],
+                                                               2 * lmax_i[sorted[n_multi - 1]]))
+                --n_multi;
+        if (n_multi < 2) n_multi = 0;
+    }
+    if (n_multi > 0) {
+        rc = matrix_masks(ctx, n_multi, sorted, lmax_i, W_TT, W_TP, W_PP, spectra, precision, out, s);
+        if (rc) return rc;
     }
     if (!mfma) {
-        // float64 / float32-compensated: one couple_matrix per mask, back to back on s
-        for (int m = 0; m < n_masks; ++m) {
+        // float64 / float32-compensated: one couple_matrix per remaining mask, back to back on s
+        for (int i = n_multi; i < n_masks; ++i) {
+            const int m = sorted[i];
             rc = couple_matrix(ctx, need_tt ? W_TT[m] : nullptr, need_tp ? W_TP[m] : nullptr,
                                need_pp ? W_PP[m] : nullptr, w_len_i[m], lmax_i[m], spectra, precision, out[m],
                                stream);

@@ -124,13 +124,14 @@ def test_batched_strip_paths_equal_single_calls(torch_gpu, ctx, precision, spect
 
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
 def test_batched_eb_multimask_equal_single_calls(torch_gpu, ctx, precision):
-    """Full matrices with EB through the multi-mask odd-L strip: four masks of
-    lmax 2100 .. 2254 (large enough for the one-mask FP32C strip's full lanes;
-    FP32C groups masks whose lmax agree mod 4, here {2254, 2250} and {2180, 2100},
-    FP64 all four), even and odd strips per group, equal to couple_matrix bitwise."""
+    """Full matrices with EB through the multi-mask odd-L strip, even and odd
+    strips per group, equal to couple_matrix bitwise.  FP32C takes masks of lmax
+    1792 and up (the one-mask strip's full lanes) in groups whose lmax agree mod 4,
+    here {2254, 2250} and {2180, 2100, 1792}, and runs lmax 1791, 300 and 40 one
+    by one; FP64 groups all eight."""
     from paper_2602_15605_amd import couple
     torch = torch_gpu
-    lmaxes = [2100, 2250, 2180, 2254]
+    lmaxes = [2100, 2250, 300, 2180, 2254, 40, 1791, 1792]
     Ws = _rand_windows(lmaxes, 12)
     dW = [[torch.as_tensor(w[s]).cuda() for w in Ws] for s in range(3)]
     for spectra in (("TT", "EE", "BB", "EB"), ("EB",)):
